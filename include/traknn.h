@@ -1,0 +1,179 @@
+/*
+ * traknn.h -- C ABI of the TRAKNN hot path on AMD Instinct MI355X (gfx950).
+ *
+ * TRAKNN (Coulaud & Faranda, "Efficient Trajectory Aware Spatiotemporal kNN
+ * for Rare Meteorological Trajectory Detection") scores every length-L
+ * trajectory of a sequence of T gridded fields by the mean squared distance to
+ * its k nearest non-overlapping trajectories. This library computes, exactly
+ * up to floating-point rounding:
+ *
+ *   d(i,j)   = ||x_i||^2 + ||x_j||^2 - 2 <x_i, x_j>           (Eq. 4, on MFMA)
+ *   D_L(i,j) = sum_{m<L} d(i+m, j+m)                           (Eq. 2, via Eq. 5)
+ *   N_t      = the k smallest (D_L(t,j), j) over j with |t-j| >= L
+ *   s_t      = (1/k) sum_{j in N_t} D_L(t,j)                    (Eq. 3)
+ *
+ * and the gradient of sum_t w_t s_t with respect to the fields, the neighbour
+ * sets held fixed.
+ *
+ * Conventions shared by every entry point
+ *   - All array pointers are DEVICE pointers (hipMalloc'd or equivalent) owned
+ *     by the caller. The library never allocates, frees or keeps device memory;
+ *     scratch space is the caller's workspace buffer.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream). Work
+ *     is enqueued asynchronously on it; results are ready when the stream is.
+ *   - Indices are 0-based. Trajectory t covers fields t .. t+L-1, so a length-L
+ *     run has n'_L = T - L + 1 trajectories.
+ *   - The exclusion zone is |t - j| >= L (the paper's e = L - 1).
+ *   - Ties in distance are broken by the smaller neighbour index, so neighbour
+ *     lists are in ascending (distance, index) order and unique.
+ *   - Return value: TRAKNN_OK (0) or a negative TRAKNN_ERR_* code. Arguments are
+ *     validated before anything is enqueued; on an error nothing is enqueued.
+ *     No C++ exception crosses this boundary. Asynchronous device faults
+ *     surface at the caller's next synchronisation.
+ *   - Inputs must be finite. This is not checked on the hot path.
+ *   - There is no CPU fallback: every computation runs in this library's HIP
+ *     kernels on the current device.
+ */
+#ifndef TRAKNN_H
+#define TRAKNN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define TRAKNN_OK 0
+#define TRAKNN_ERR_INVALID_ARG (-1) /* a size, pointer, stride or alignment is invalid */
+#define TRAKNN_ERR_UNSUPPORTED (-2) /* valid request outside what this build implements */
+#define TRAKNN_ERR_WORKSPACE (-3)   /* workspace pointer NULL/misaligned or too small */
+#define TRAKNN_ERR_HIP (-4)         /* a HIP runtime call or kernel launch failed */
+
+/* Precision of the Gram contraction (Eq. 4). In every mode the fields are first
+ * centred per grid cell in FP64 (distances are translation invariant), squared
+ * norms and the epilogue N_i + N_j - 2G are FP64, distances are stored FP32 and
+ * trajectory sums (Eq. 2/5) are FP64.
+ *   TRAKNN_FP32   : centred fields rounded to FP32, FP32 MFMA (32x32x2).
+ *   TRAKNN_BF16X3 : centred fields split hi = bf16(x), lo = bf16(x - hi);
+ *                   G = hi.hi' + hi.lo' + lo.hi' on BF16 MFMA (32x32x16) with FP32
+ *                   accumulation (the lo.lo' term is dropped).
+ *   TRAKNN_FP16   : centred fields rounded to FP16, one FP16 MFMA pass (32x32x16).
+ *                   Requires |x - mean| < 65504 in every cell. */
+#define TRAKNN_FP32 0
+#define TRAKNN_BF16X3 1
+#define TRAKNN_FP16 2
+
+#define TRAKNN_MAX_L 16
+#define TRAKNN_MAX_K 64
+
+/* Problem description.
+ *   T, D        number of fields (time steps) and cells per field, >= 1.
+ *   L_min,L_max trajectory lengths, 1 <= L_min <= L_max <= TRAKNN_MAX_L. One
+ *               call emits neighbour lists for every L in [L_min, L_max]
+ *               (L_min == L_max for a single length). Multi-length sweeps need
+ *               L_min == 1.
+ *   k           neighbours per trajectory, 1 <= k <= TRAKNN_MAX_K; every length
+ *               must leave each row k candidates: T - L_max + 1 >= k + 2 L_max - 1.
+ *   precision   TRAKNN_FP32, TRAKNN_BF16X3 or TRAKNN_FP16.
+ *   row_batch   must be 0 (the whole T x T distance matrix is held in the
+ *               workspace; see traknn_plan's workspace size). */
+typedef struct {
+  int64_t T;
+  int64_t D;
+  int32_t L_min;
+  int32_t L_max;
+  int32_t k;
+  int32_t precision;
+  int64_t row_batch;
+} traknn_config;
+
+typedef struct traknn_plan_s* traknn_plan_t;
+
+/* Validate a configuration and size the workspace (paper, Algorithm 1 inputs:
+ * fields, duration, exclusion zone, k; the batch size is chosen here).
+ * Pure host code: makes no HIP call, so it can be used without a GPU.
+ *   cfg              [in]  problem description (copied; caller keeps ownership).
+ *   out              [out] new plan handle; immutable; free with
+ *                          traknn_plan_destroy. Not for concurrent use from two
+ *                          threads when timing is enabled.
+ *   workspace_bytes  [out] device bytes the caller must provide to traknn_knn
+ *                          and traknn_score_backward (one size covers both).
+ * Errors: INVALID_ARG for NULL pointers or sizes out of range; UNSUPPORTED for
+ * row_batch != 0 or a multi-length sweep with L_min != 1. */
+int traknn_plan(const traknn_config* cfg, traknn_plan_t* out,
+                size_t* workspace_bytes);
+
+/* Free a plan's host memory (and any HIP timing events it created).
+ * Errors: INVALID_ARG for NULL. */
+int traknn_plan_destroy(traknn_plan_t plan);
+
+/* Exact exclusion-zone kNN over trajectories (paper, Algorithm 1 stages 1-3:
+ * Eq. 4 Gram distances for the upper-triangular tile pairs, Eq. 5 diagonal
+ * recurrence, k smallest with |t - j| > e).
+ *   X         [in]  T x D fields, FP32, row-major with row stride ldx floats;
+ *                   16-byte aligned, ldx >= D, ldx % 4 == 0.
+ *   workspace [in]  >= workspace_bytes from traknn_plan, 256-byte aligned;
+ *                   contents are scratch (overwritten).
+ *   nbr_idx   [out] int32 [L_max-L_min+1][T-L_min+1][k]; block for length L is
+ *                   at offset (L-L_min)*(T-L_min+1)*k. Row t lists the k
+ *                   neighbours of trajectory t in ascending (distance, index).
+ *                   Rows t >= T-L+1 (which do not exist for that L) hold -1.
+ *   nbr_dist  [out] FP64, same shape: D_L(t, nbr_idx) (squared); +inf in
+ *                   non-existent rows.
+ * Errors: INVALID_ARG (NULL, stride, alignment), WORKSPACE, HIP. */
+int traknn_knn(traknn_plan_t plan, const float* X, int64_t ldx, void* workspace,
+               size_t workspace_bytes, int32_t* nbr_idx, double* nbr_dist,
+               void* stream);
+
+/* Rarity score (paper, Eq. 3): s_t = (1/k) * sum of the row of nbr_dist, summed
+ * in rank order in FP64.
+ *   nbr_dist [in]  as written by traknn_knn for the same plan.
+ *   scores   [out] FP64 [L_max-L_min+1][T-L_min+1]; NaN in non-existent rows.
+ * Errors: INVALID_ARG, HIP. */
+int traknn_score(traknn_plan_t plan, const double* nbr_dist, double* scores,
+                 void* stream);
+
+/* Gradient of F = sum_t grad_scores[t] * s_t with respect to X, the neighbour
+ * sets held fixed (differentiating Eq. 2 inside Eq. 3):
+ *   dF/dx_a = (2/k) sum_t w_t sum_{j in N_t} sum_{m<L}
+ *             ([a = t+m] - [a = j+m]) (x_{t+m} - x_{j+m}).
+ * Deterministic: every row of grad_X is gathered in a fixed order, no atomics
+ * on floating-point data. No distance is needed, so none is stored or
+ * recomputed beyond the field differences themselves.
+ *   X           [in]  the fields passed to traknn_knn (same layout rules).
+ *   nbr_idx     [in]  int32 [T-L+1][k] from traknn_knn (single length only).
+ *   grad_scores [in]  FP64 [T-L+1] upstream weights w_t.
+ *   grad_X      [out] FP32 T x D, row stride ldg (ldg >= D); every row written
+ *                     (zeros where no term touches it).
+ *   workspace   [in]  as for traknn_knn.
+ * Errors: INVALID_ARG, WORKSPACE, HIP; UNSUPPORTED if L_min != L_max. */
+int traknn_score_backward(traknn_plan_t plan, const float* X, int64_t ldx,
+                          const int32_t* nbr_idx, const double* grad_scores,
+                          float* grad_X, int64_t ldg, void* workspace,
+                          size_t workspace_bytes, void* stream);
+
+/* Static description of a status code; never NULL. */
+const char* traknn_status_string(int status);
+
+/* Per-stage timing of the most recent traknn_knn call on this plan.
+ * When enabled, traknn_knn records HIP events on its stream between its
+ * stages; traknn_stage_times then waits for the last event and returns the
+ * elapsed milliseconds of each stage in launch order:
+ *   0 centre statistics, 1 centre/convert/norms, 2 Gram + distance epilogue,
+ *   3 window recurrence + partial top-k, 4 top-k merge.
+ *   enable   [in]  nonzero to record events from the next traknn_knn call on.
+ *   ms       [out] host array of at least max_stages doubles.
+ *   n_stages [out] number of stages written.
+ * Errors: INVALID_ARG; UNSUPPORTED if timing was not enabled or no call has
+ * been timed yet; HIP. */
+int traknn_set_timing(traknn_plan_t plan, int enable);
+int traknn_stage_times(traknn_plan_t plan, double* ms, int max_stages,
+                       int* n_stages);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TRAKNN_H */

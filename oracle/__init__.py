@@ -99,6 +99,16 @@ def snapshot_dist(X) -> np.ndarray:
     return S
 
 
+def traj_dist_from_snapshot(S, L: int) -> np.ndarray:
+    """D_L (n' x n') as direct sums over m of a snapshot matrix S (T x T)."""
+    S = np.ascontiguousarray(S, dtype=np.float64)
+    T = S.shape[0]
+    n = T - L + 1
+    Dm = np.empty((n, n), dtype=np.float64)
+    _check(_load().oracle_traj_dist_from_snapshot(S, T, int(L), Dm), "traj_dist")
+    return Dm
+
+
 def traj_dist(X, L: int) -> np.ndarray:
     """Full trajectory distance matrix D_L (n' x n'), Eq. 2 as a direct sum."""
     S = snapshot_dist(X)

@@ -1,0 +1,279 @@
+// C ABI of the TRAKNN hot path: planning, argument validation, workspace
+// layout and the launch sequence. No C++ exception crosses this boundary and
+// nothing is enqueued unless every argument has been accepted.
+#include <climits>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+
+#include "internal.h"
+
+using namespace traknn;
+
+namespace {
+
+constexpr size_t WS_ALIGN = 256;
+constexpr int64_t MAX_T = 1 << 20;       // int32 indices with headroom
+constexpr int64_t MAX_D = (int64_t)1 << 28;
+constexpr size_t MAX_WIN_LDS = 64 * 1024;
+constexpr int64_t WIN_TARGET_UNITS = 4096;
+constexpr int MAX_SPLITS = 16;
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+int fail_hip(hipError_t e) { return e == hipSuccess ? TRAKNN_OK : TRAKNN_ERR_HIP; }
+
+// Choose rows per window wave and column splits. R = 32 keeps the diagonal
+// chunk's LDS staging and list storage small; R = 4 serves large k * NL (up to
+// 16 lengths x 64 neighbours).
+bool plan_window(traknn_plan_s* p) {
+  const int k = p->cfg.k;
+  int rows = 32;
+  size_t lds = window_lds_bytes(p->cfg.L_max, p->NL, k, rows);
+  if (lds > MAX_WIN_LDS) {
+    rows = 4;
+    lds = window_lds_bytes(p->cfg.L_max, p->NL, k, rows);
+    if (lds > MAX_WIN_LDS) return false;
+  }
+  const int64_t nrb = (p->np0 + rows - 1) / rows;
+  const int64_t nchunks = (p->np0 + rows - 1 + 63) / 64;
+  int64_t W = (WIN_TARGET_UNITS + nrb - 1) / nrb;
+  if (W > MAX_SPLITS) W = MAX_SPLITS;
+  if (W > nchunks) W = nchunks;
+  if (W < 1) W = 1;
+  p->win_rows = rows;
+  p->win_splits = (int)W;
+  p->win_units = nrb * W;
+  p->win_lds = lds;
+  return true;
+}
+
+void plan_layout(traknn_plan_s* p) {
+  Layout& L = p->lay;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align_up(o + bytes, WS_ALIGN);
+    return at;
+  };
+  const int prec = p->cfg.precision;
+  L.mu_part = take((size_t)p->tchunks * p->D * sizeof(double));
+  L.mu = take((size_t)p->D * sizeof(double));
+  L.norm = take((size_t)p->Tpad * sizeof(double));
+  L.xc = take((size_t)p->Tpad * p->Dpad * elem_bytes(prec));
+  L.S = take((size_t)p->T * p->ldS * sizeof(float));
+  const size_t nparts = (size_t)p->win_splits * p->NL * p->np0 * p->cfg.k;
+  L.part_d = take(nparts * sizeof(double));
+  L.part_i = take(nparts * sizeof(int32_t));
+  const size_t np = (size_t)(p->T - p->cfg.L_min + 1);
+  L.bw_cnt = take(np * sizeof(int32_t));
+  L.bw_ptr = take((np + 1) * sizeof(int32_t));
+  L.bw_fill = take(np * sizeof(int32_t));
+  L.bw_rev = take(np * p->cfg.k * sizeof(int32_t));
+  L.total = o;
+}
+
+int check_x(const traknn_plan_s* p, const float* X, int64_t ldx) {
+  if (!X || ldx < p->D || ldx % 4 != 0 || !aligned(X, 16))
+    return TRAKNN_ERR_INVALID_ARG;
+  return TRAKNN_OK;
+}
+
+int check_ws(const traknn_plan_s* p, const void* ws, size_t bytes) {
+  if (!ws || !aligned(ws, WS_ALIGN) || bytes < p->lay.total)
+    return TRAKNN_ERR_WORKSPACE;
+  return TRAKNN_OK;
+}
+
+template <typename T>
+T* at(void* ws, size_t off) {
+  return (T*)((char*)ws + off);
+}
+
+int record(traknn_plan_s* p, int slot, hipStream_t s) {
+  if (!p->timing) return TRAKNN_OK;
+  return fail_hip(hipEventRecord(p->ev[slot], s));
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* traknn_status_string(int status) {
+  switch (status) {
+    case TRAKNN_OK:
+      return "ok";
+    case TRAKNN_ERR_INVALID_ARG:
+      return "invalid argument";
+    case TRAKNN_ERR_UNSUPPORTED:
+      return "unsupported configuration";
+    case TRAKNN_ERR_WORKSPACE:
+      return "workspace missing, misaligned or too small";
+    case TRAKNN_ERR_HIP:
+      return "HIP runtime or kernel launch failure";
+    default:
+      return "unknown status";
+  }
+}
+
+int traknn_plan(const traknn_config* cfg, traknn_plan_t* out,
+                size_t* workspace_bytes) {
+  if (!cfg || !out || !workspace_bytes) return TRAKNN_ERR_INVALID_ARG;
+  *out = nullptr;
+  const traknn_config c = *cfg;
+  if (c.T < 1 || c.T > MAX_T || c.D < 1 || c.D > MAX_D)
+    return TRAKNN_ERR_INVALID_ARG;
+  if (c.L_min < 1 || c.L_max < c.L_min || c.L_max > TRAKNN_MAX_L)
+    return TRAKNN_ERR_INVALID_ARG;
+  if (c.k < 1 || c.k > TRAKNN_MAX_K) return TRAKNN_ERR_INVALID_ARG;
+  if (c.precision != TRAKNN_FP32 && c.precision != TRAKNN_BF16X3 &&
+      c.precision != TRAKNN_FP16)
+    return TRAKNN_ERR_INVALID_ARG;
+  // every row of every length needs k candidates outside its exclusion zone
+  if (c.T - c.L_max + 1 < (int64_t)c.k + 2 * c.L_max - 1)
+    return TRAKNN_ERR_INVALID_ARG;
+  if (c.row_batch != 0) return TRAKNN_ERR_UNSUPPORTED;
+  if (c.L_min != c.L_max && c.L_min != 1) return TRAKNN_ERR_UNSUPPORTED;
+
+  traknn_plan_s* p = new (std::nothrow) traknn_plan_s();
+  if (!p) return TRAKNN_ERR_INVALID_ARG;
+  p->cfg = c;
+  p->T = c.T;
+  p->D = c.D;
+  p->Dpad = round_up(c.D, stage_k(c.precision));
+  p->Tpad = round_up(c.T, GRAM_TILE);
+  p->ldS = round_up(c.T, 64);
+  p->np0 = c.T - c.L_min + 1;
+  p->NL = c.L_max - c.L_min + 1;
+  p->nb = (int)(p->Tpad / GRAM_TILE);
+  p->ntiles = (int64_t)p->nb * (p->nb + 1) / 2;
+  p->tchunks = (int)((c.T + COLSTAT_ROWS - 1) / COLSTAT_ROWS);
+  if (!plan_window(p)) {
+    delete p;
+    return TRAKNN_ERR_UNSUPPORTED;
+  }
+  plan_layout(p);
+  *out = p;
+  *workspace_bytes = p->lay.total;
+  return TRAKNN_OK;
+}
+
+int traknn_plan_destroy(traknn_plan_t plan) {
+  if (!plan) return TRAKNN_ERR_INVALID_ARG;
+  if (plan->events_ready)
+    for (int i = 0; i <= NUM_STAGES; ++i) (void)hipEventDestroy(plan->ev[i]);
+  delete plan;
+  return TRAKNN_OK;
+}
+
+int traknn_set_timing(traknn_plan_t plan, int enable) {
+  if (!plan) return TRAKNN_ERR_INVALID_ARG;
+  if (enable && !plan->events_ready) {
+    for (int i = 0; i <= NUM_STAGES; ++i) {
+      if (hipEventCreate(&plan->ev[i]) != hipSuccess) {
+        for (int q = 0; q < i; ++q) (void)hipEventDestroy(plan->ev[q]);
+        return TRAKNN_ERR_HIP;
+      }
+    }
+    plan->events_ready = 1;
+  }
+  plan->timing = enable ? 1 : 0;
+  plan->timed_calls = 0;
+  return TRAKNN_OK;
+}
+
+int traknn_stage_times(traknn_plan_t plan, double* ms, int max_stages,
+                       int* n_stages) {
+  if (!plan || !ms || !n_stages || max_stages < 1) return TRAKNN_ERR_INVALID_ARG;
+  if (!plan->events_ready || plan->timed_calls == 0) return TRAKNN_ERR_UNSUPPORTED;
+  if (hipEventSynchronize(plan->ev[NUM_STAGES]) != hipSuccess) return TRAKNN_ERR_HIP;
+  const int n = max_stages < NUM_STAGES ? max_stages : NUM_STAGES;
+  for (int i = 0; i < n; ++i) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, plan->ev[i], plan->ev[i + 1]) != hipSuccess)
+      return TRAKNN_ERR_HIP;
+    ms[i] = (double)t;
+  }
+  *n_stages = n;
+  return TRAKNN_OK;
+}
+
+int traknn_knn(traknn_plan_t plan, const float* X, int64_t ldx, void* workspace,
+               size_t workspace_bytes, int32_t* nbr_idx, double* nbr_dist,
+               void* stream) {
+  if (!plan || !nbr_idx || !nbr_dist) return TRAKNN_ERR_INVALID_ARG;
+  int rc = check_x(plan, X, ldx);
+  if (rc) return rc;
+  rc = check_ws(plan, workspace, workspace_bytes);
+  if (rc) return rc;
+  const traknn_config& c = plan->cfg;
+  hipStream_t s = (hipStream_t)stream;
+  const Layout& L = plan->lay;
+  double* mu_part = at<double>(workspace, L.mu_part);
+  double* mu = at<double>(workspace, L.mu);
+  double* norm = at<double>(workspace, L.norm);
+  void* xc = at<char>(workspace, L.xc);
+  float* S = at<float>(workspace, L.S);
+  double* part_d = at<double>(workspace, L.part_d);
+  int32_t* part_i = at<int32_t>(workspace, L.part_i);
+
+  if ((rc = record(plan, 0, s))) return rc;
+  if ((rc = fail_hip(launch_colstats(X, ldx, plan->T, plan->D, plan->tchunks,
+                                     mu_part, mu, s))))
+    return rc;
+  if ((rc = record(plan, 1, s))) return rc;
+  if ((rc = fail_hip(launch_centre_convert(X, ldx, plan->T, plan->D, plan->Tpad,
+                                           plan->Dpad, c.precision, mu, xc,
+                                           norm, s))))
+    return rc;
+  if ((rc = record(plan, 2, s))) return rc;
+  if ((rc = fail_hip(launch_gram(xc, norm, plan->T, plan->Dpad, plan->nb,
+                                 plan->ntiles, c.precision, S, plan->ldS, s))))
+    return rc;
+  if ((rc = record(plan, 3, s))) return rc;
+  if ((rc = fail_hip(launch_window_topk(S, plan->ldS, plan->T, c.L_min, c.L_max,
+                                        c.k, plan->win_rows, plan->win_splits,
+                                        plan->win_units, plan->win_lds, part_d,
+                                        part_i, s))))
+    return rc;
+  if ((rc = record(plan, 4, s))) return rc;
+  if ((rc = fail_hip(launch_merge(part_d, part_i, plan->T, c.L_min, c.L_max, c.k,
+                                  plan->win_splits, nbr_idx, nbr_dist, s))))
+    return rc;
+  if ((rc = record(plan, 5, s))) return rc;
+  if (plan->timing) plan->timed_calls++;
+  return TRAKNN_OK;
+}
+
+int traknn_score(traknn_plan_t plan, const double* nbr_dist, double* scores,
+                 void* stream) {
+  if (!plan || !nbr_dist || !scores) return TRAKNN_ERR_INVALID_ARG;
+  const traknn_config& c = plan->cfg;
+  return fail_hip(launch_score(nbr_dist, plan->T, c.L_min, c.L_max, c.k, scores,
+                               (hipStream_t)stream));
+}
+
+int traknn_score_backward(traknn_plan_t plan, const float* X, int64_t ldx,
+                          const int32_t* nbr_idx, const double* grad_scores,
+                          float* grad_X, int64_t ldg, void* workspace,
+                          size_t workspace_bytes, void* stream) {
+  if (!plan || !nbr_idx || !grad_scores || !grad_X) return TRAKNN_ERR_INVALID_ARG;
+  int rc = check_x(plan, X, ldx);
+  if (rc) return rc;
+  if (ldg < plan->D) return TRAKNN_ERR_INVALID_ARG;
+  rc = check_ws(plan, workspace, workspace_bytes);
+  if (rc) return rc;
+  const traknn_config& c = plan->cfg;
+  if (c.L_min != c.L_max) return TRAKNN_ERR_UNSUPPORTED;
+  const Layout& L = plan->lay;
+  return fail_hip(launch_backward(
+      X, ldx, plan->T, plan->D, c.L_max, c.k, nbr_idx, grad_scores, grad_X, ldg,
+      at<int32_t>(workspace, L.bw_cnt), at<int32_t>(workspace, L.bw_ptr),
+      at<int32_t>(workspace, L.bw_fill), at<int32_t>(workspace, L.bw_rev),
+      (hipStream_t)stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,278 @@
+// Symmetric Gram product and distance epilogue (paper, Algorithm 1 stage 1 and
+// Eq. 4): for every tile pair I <= J of 256 fields,
+//   G_IJ = Xc_I Xc_J^T          (MFMA, FP32 accumulation)
+//   d(i,j) = N_i + N_j - 2 G_ij (FP64), stored FP32 at (i,j) and (j,i).
+// Only the upper triangle of tile pairs is computed, which halves the
+// contraction as the paper's symmetric batching does.
+//
+// Tiling for gfx950: 256 threads = 4 wave64s in a 2x2 arrangement, each wave
+// owning a 128x128 block = 4x4 MFMA 32x32 blocks held in accumulation
+// registers. Every K stage brings 128 bytes of each of the 512 operand rows
+// into LDS (2 x 32 KB), double buffered. Rows are stored with their eight
+// 16-byte chunks XOR-swizzled by the row index so that the ds_read_b128
+// fragment loads of 32 consecutive rows spread over all banks.
+//
+// Workgroups are mapped XCD-aware: the hardware deals consecutive workgroup
+// ids round-robin to the 8 XCDs, so each XCD is handed a contiguous run of a
+// grouped tile order (4 block-rows x successive block-columns). The ~32 tiles
+// an XCD runs at once then share 4 A panels and ~8 B panels in its L2.
+#include "internal.h"
+
+namespace traknn {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int TILE = GRAM_TILE;
+constexpr int RB = GRAM_ROW_BYTES;          // bytes per row per stage
+constexpr int OPER_BYTES = TILE * RB;       // one operand tile in LDS (32 KB)
+constexpr int CHUNKS_PER_THREAD = TILE * (RB / 16) / GRAM_THREADS;  // 8
+
+__device__ __forceinline__ int swz(int row, int chunk) {
+  return ((chunk ^ (row & 7)) << 4);
+}
+
+// Tile id -> (I, J), I <= J, in the XCD-aware grouped order described above.
+__device__ __forceinline__ bool decode_tile(int64_t wg, int nb, int64_t ntiles,
+                                            int& I, int& J) {
+  const int64_t per = (ntiles + NUM_XCD - 1) / NUM_XCD;
+  const int64_t lin = (wg % NUM_XCD) * per + wg / NUM_XCD;
+  if (lin >= ntiles) return false;
+  int64_t u = lin;
+  for (int I0 = 0; I0 < nb; I0 += GRAM_GROUP_ROWS) {
+    const int gm = nb - I0 < GRAM_GROUP_ROWS ? nb - I0 : GRAM_GROUP_ROWS;
+    const int64_t cnt = (int64_t)gm * nb - ((int64_t)gm * I0 + (int64_t)gm * (gm - 1) / 2);
+    if (u < cnt) {
+      const int64_t head = (int64_t)gm * (gm - 1) / 2;
+      if (u < head) {
+        // head columns J = I0 + m hold m + 1 rows each
+        int m = 0;
+        while ((int64_t)(m + 1) * (m + 2) / 2 <= u) ++m;
+        J = I0 + m;
+        I = I0 + (int)(u - (int64_t)m * (m + 1) / 2);
+      } else {
+        const int64_t v = u - head;
+        J = I0 + gm - 1 + (int)(v / gm);
+        I = I0 + (int)(v % gm);
+      }
+      return true;
+    }
+    u -= cnt;
+  }
+  return false;
+}
+
+template <int PREC>
+__device__ __forceinline__ void compute_stage(const char* __restrict__ A,
+                                              const char* __restrict__ B,
+                                              int wm, int wn, int lane,
+                                              f32x16 (&acc)[4][4]) {
+  const int r32 = lane & 31;
+  const int half = lane >> 5;
+  if constexpr (PREC == TRAKNN_BF16X3) {
+#pragma unroll
+    for (int kk = 0; kk < 2; ++kk) {
+      const int g = 2 * kk + half;  // 8-element group this lane supplies
+      bf16x8 ah[4], al[4], bh[4], bl[4];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int ra = wm * 128 + b * 32 + r32;
+        const int rb = wn * 128 + b * 32 + r32;
+        ah[b] = *(const bf16x8*)(A + ra * RB + swz(ra, 2 * g));
+        al[b] = *(const bf16x8*)(A + ra * RB + swz(ra, 2 * g + 1));
+        bh[b] = *(const bf16x8*)(B + rb * RB + swz(rb, 2 * g));
+        bl[b] = *(const bf16x8*)(B + rb * RB + swz(rb, 2 * g + 1));
+      }
+#pragma unroll
+      for (int bm = 0; bm < 4; ++bm)
+#pragma unroll
+        for (int bn = 0; bn < 4; ++bn) {
+          acc[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[bm], bh[bn], acc[bm][bn], 0, 0, 0);
+          acc[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[bm], bl[bn], acc[bm][bn], 0, 0, 0);
+          acc[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[bm], bh[bn], acc[bm][bn], 0, 0, 0);
+        }
+    }
+  } else if constexpr (PREC == TRAKNN_FP16) {
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int g = 2 * kk + half;
+      f16x8 a[4], b[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int ra = wm * 128 + q * 32 + r32;
+        const int rb = wn * 128 + q * 32 + r32;
+        a[q] = *(const f16x8*)(A + ra * RB + swz(ra, g));
+        b[q] = *(const f16x8*)(B + rb * RB + swz(rb, g));
+      }
+#pragma unroll
+      for (int bm = 0; bm < 4; ++bm)
+#pragma unroll
+        for (int bn = 0; bn < 4; ++bn)
+          acc[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a[bm], b[bn], acc[bm][bn], 0, 0, 0);
+    }
+  } else {
+    // FP32: each lane reads 4 consecutive k of chunk 2s + half; MFMA e of the
+    // four consumes element e, so the 4 MFMAs x 2 lane halves cover 8 k.
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int c = 2 * s + half;
+      f32x4 a[4], b[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int ra = wm * 128 + q * 32 + r32;
+        const int rb = wn * 128 + q * 32 + r32;
+        a[q] = *(const f32x4*)(A + ra * RB + swz(ra, c));
+        b[q] = *(const f32x4*)(B + rb * RB + swz(rb, c));
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int bm = 0; bm < 4; ++bm)
+#pragma unroll
+          for (int bn = 0; bn < 4; ++bn)
+            acc[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[bm][e], b[bn][e], acc[bm][bn], 0, 0, 0);
+    }
+  }
+}
+
+template <int PREC>
+__global__ __launch_bounds__(GRAM_THREADS, 1) void gram_kernel(
+    const char* __restrict__ xc, int64_t pitch, int nstages,
+    const double* __restrict__ norm, int64_t T, int nb, int64_t ntiles,
+    float* __restrict__ S, int64_t ldS) {
+  __shared__ __attribute__((aligned(16))) char lds[GRAM_STAGES * 2 * OPER_BYTES];
+  int I, J;
+  if (!decode_tile(blockIdx.x, nb, ntiles, I, J)) return;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6;
+  const int wm = w >> 1, wn = w & 1;
+  const char* Ag = xc + (int64_t)I * TILE * pitch;
+  const char* Bg = xc + (int64_t)J * TILE * pitch;
+
+  i32x4 ra[CHUNKS_PER_THREAD], rb[CHUNKS_PER_THREAD];
+  auto gload = [&](int st) {
+#pragma unroll
+    for (int u = 0; u < CHUNKS_PER_THREAD; ++u) {
+      const int q = tid + GRAM_THREADS * u;
+      const int row = q >> 3, c = q & 7;
+      const int64_t off = (int64_t)row * pitch + (int64_t)st * RB + c * 16;
+      ra[u] = *(const i32x4*)(Ag + off);
+      rb[u] = *(const i32x4*)(Bg + off);
+    }
+  };
+  auto lstore = [&](int buf) {
+    char* A = lds + buf * 2 * OPER_BYTES;
+    char* B = A + OPER_BYTES;
+#pragma unroll
+    for (int u = 0; u < CHUNKS_PER_THREAD; ++u) {
+      const int q = tid + GRAM_THREADS * u;
+      const int row = q >> 3, c = q & 7;
+      *(i32x4*)(A + row * RB + swz(row, c)) = ra[u];
+      *(i32x4*)(B + row * RB + swz(row, c)) = rb[u];
+    }
+  };
+
+  f32x16 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.f;
+
+  gload(0);
+  lstore(0);
+  __syncthreads();
+  for (int st = 0; st < nstages; ++st) {
+    const int buf = st & 1;
+    const bool more = st + 1 < nstages;
+    if (more) gload(st + 1);
+    const char* A = lds + buf * 2 * OPER_BYTES;
+    compute_stage<PREC>(A, A + OPER_BYTES, wm, wn, lane, acc);
+    if (more) lstore(buf ^ 1);
+    __syncthreads();
+  }
+
+  // Epilogue: accumulator r of lane l in a 32x32 block holds
+  // row 8*(r/4) + 4*(l/32) + r%4, column l%32 of that block.
+  const bool diag = I == J;
+#pragma unroll
+  for (int bm = 0; bm < 4; ++bm) {
+#pragma unroll
+    for (int bn = 0; bn < 4; ++bn) {
+      const int64_t j = (int64_t)J * TILE + wn * 128 + bn * 32 + (lane & 31);
+      const double nj = j < T ? norm[j] : 0.0;
+#pragma unroll
+      for (int r4 = 0; r4 < 4; ++r4) {
+        const int64_t i0 = (int64_t)I * TILE + wm * 128 + bm * 32 + 8 * r4 + 4 * (lane >> 5);
+        float f[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int64_t i = i0 + e;
+          const double ni = i < T ? norm[i] : 0.0;
+          double v = ni + nj - 2.0 * (double)acc[bm][bn][4 * r4 + e];
+          f[e] = v > 0.0 ? (float)v : 0.f;
+        }
+        if (j >= T) continue;
+        if (!diag) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (i0 + e < T) S[(i0 + e) * ldS + j] = f[e];
+          if (i0 + 3 < T) {
+            *(f32x4*)(S + j * ldS + i0) = f32x4{f[0], f[1], f[2], f[3]};
+          } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+              if (i0 + e < T) S[j * ldS + i0 + e] = f[e];
+          }
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int64_t i = i0 + e;
+            if (i >= T) continue;
+            if (i < j) {
+              S[i * ldS + j] = f[e];
+              S[j * ldS + i] = f[e];
+            } else if (i == j) {
+              S[i * ldS + i] = 0.f;
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_gram(const void* xc, const double* norm, int64_t T,
+                       int64_t Dpad, int nb, int64_t ntiles, int precision,
+                       float* S, int64_t ldS, hipStream_t s) {
+  const int64_t pitch = Dpad * elem_bytes(precision);
+  const int nstages = (int)(Dpad / stage_k(precision));
+  const int64_t per = (ntiles + NUM_XCD - 1) / NUM_XCD;
+  dim3 grid((unsigned)(per * NUM_XCD));
+  const char* x = (const char*)xc;
+  switch (precision) {
+    case TRAKNN_FP32:
+      hipLaunchKernelGGL(gram_kernel<TRAKNN_FP32>, grid, dim3(GRAM_THREADS), 0,
+                         s, x, pitch, nstages, norm, T, nb, ntiles, S, ldS);
+      break;
+    case TRAKNN_BF16X3:
+      hipLaunchKernelGGL(gram_kernel<TRAKNN_BF16X3>, grid, dim3(GRAM_THREADS),
+                         0, s, x, pitch, nstages, norm, T, nb, ntiles, S, ldS);
+      break;
+    default:
+      hipLaunchKernelGGL(gram_kernel<TRAKNN_FP16>, grid, dim3(GRAM_THREADS), 0,
+                         s, x, pitch, nstages, norm, T, nb, ntiles, S, ldS);
+      break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace traknn

@@ -1,0 +1,103 @@
+// Internal declarations shared by the TRAKNN HIP translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "traknn.h"
+
+namespace traknn {
+
+// ---------------------------------------------------------------------------
+// Gram tiling (Eq. 4 stage). One workgroup owns a GRAM_TILE x GRAM_TILE block
+// of the distance matrix; every K stage moves GRAM_ROW_BYTES of each of the
+// 2 * GRAM_TILE operand rows through LDS.
+// ---------------------------------------------------------------------------
+constexpr int GRAM_TILE = 256;
+constexpr int GRAM_THREADS = 256;
+constexpr int GRAM_ROW_BYTES = 128;
+constexpr int GRAM_STAGES = 2;
+constexpr int GRAM_GROUP_ROWS = 4;  // block-rows per L2 locality group
+constexpr int NUM_XCD = 8;
+
+// K elements one stage covers: 32 FP32 values, 32 (hi, lo) BF16 pairs or 64
+// FP16 values -- always 128 bytes of a centred row.
+inline int stage_k(int precision) { return precision == TRAKNN_FP16 ? 64 : 32; }
+inline int elem_bytes(int precision) { return precision == TRAKNN_FP16 ? 2 : 4; }
+
+// ---------------------------------------------------------------------------
+// Window / top-k stage.
+// ---------------------------------------------------------------------------
+constexpr int WIN_WAVE = 64;
+
+// Per-stage event slots for optional timing.
+constexpr int NUM_STAGES = 5;
+constexpr int COLSTAT_ROWS = 64;  // rows per partial column-sum block
+
+struct Layout {
+  size_t mu_part, mu, norm, xc, S, part_d, part_i;  // forward
+  size_t bw_cnt, bw_ptr, bw_fill, bw_rev;            // backward
+  size_t total;
+};
+
+}  // namespace traknn
+
+struct traknn_plan_s {
+  traknn_config cfg;
+  int64_t T, D;
+  int64_t Dpad;      // D rounded up to the Gram stage depth (zero padded)
+  int64_t Tpad;      // T rounded up to GRAM_TILE (zero rows)
+  int64_t ldS;       // row stride of the T x T distance matrix, floats
+  int64_t np0;       // T - L_min + 1: rows of every output block
+  int NL;            // L_max - L_min + 1
+  int nb;            // Tpad / GRAM_TILE
+  int64_t ntiles;    // nb (nb + 1) / 2 upper-triangular tile pairs
+  int tchunks;       // ceil(T / COLSTAT_ROWS)
+  int win_rows;      // rows per window wave (R)
+  int win_splits;    // column splits per row block (W)
+  int64_t win_units; // row blocks * splits
+  size_t win_lds;    // bytes of LDS per window wave
+  traknn::Layout lay;
+  // timing
+  int timing;
+  int timed_calls;
+  int events_ready;
+  hipEvent_t ev[traknn::NUM_STAGES + 1];
+};
+
+namespace traknn {
+
+// prep.hip
+hipError_t launch_colstats(const float* X, int64_t ldx, int64_t T, int64_t D,
+                           int tchunks, double* mu_part, double* mu,
+                           hipStream_t s);
+hipError_t launch_centre_convert(const float* X, int64_t ldx, int64_t T,
+                                 int64_t D, int64_t Tpad, int64_t Dpad,
+                                 int precision, const double* mu, void* xc,
+                                 double* norm, hipStream_t s);
+// gram.hip
+hipError_t launch_gram(const void* xc, const double* norm, int64_t T,
+                       int64_t Dpad, int nb, int64_t ntiles, int precision,
+                       float* S, int64_t ldS, hipStream_t s);
+// window_topk.hip
+hipError_t launch_window_topk(const float* S, int64_t ldS, int64_t T, int L_min,
+                              int L_max, int k, int rows, int splits,
+                              int64_t units, size_t lds_bytes, double* part_d,
+                              int32_t* part_i, hipStream_t s);
+hipError_t launch_merge(const double* part_d, const int32_t* part_i, int64_t T,
+                        int L_min, int L_max, int k, int splits, int32_t* idx,
+                        double* dist, hipStream_t s);
+hipError_t launch_score(const double* dist, int64_t T, int L_min, int L_max,
+                        int k, double* scores, hipStream_t s);
+// backward.hip
+hipError_t launch_backward(const float* X, int64_t ldx, int64_t T, int64_t D,
+                           int L, int k, const int32_t* idx, const double* w,
+                           float* g, int64_t ldg, int32_t* cnt, int32_t* ptr,
+                           int32_t* fill, int32_t* rev, hipStream_t s);
+
+// Window stage sizing shared by the planner and the launcher.
+size_t window_lds_bytes(int L_max, int NL, int k, int rows);
+
+}  // namespace traknn

@@ -1,0 +1,145 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function the
+header declares, and the planner and argument validation reject what they
+must, with the documented codes, before anything is enqueued."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2603_02059_amd import traknn as tk
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "traknn.h")
+
+
+def _declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(traknn_[a-z_]+)\s*\(", src)))
+
+
+def test_header_functions_are_exported():
+    names = _declared_functions()
+    assert set(names) == set(tk.EXPORTS)
+    lib = ctypes.CDLL(tk.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+    out = subprocess.run(["nm", "-D", "--defined-only", tk.LIB_PATH],
+                         capture_output=True, text=True, check=True).stdout
+    for n in names:
+        assert re.search(rf"\bT {n}\b", out), n
+
+
+def test_status_strings():
+    for code in (0, -1, -2, -3, -4):
+        assert tk.status_string(code)
+    assert tk.status_string(-99) == "unknown status"
+
+
+def _plan_code(**kw):
+    cfg = dict(T=512, D=1024, L_min=3, L_max=3, k=5, precision=1, row_batch=0)
+    cfg.update(kw)
+    try:
+        h, ws = tk.traknn_plan(**cfg)
+    except tk.TraknnError as e:
+        return e.code, None
+    tk.traknn_plan_destroy(h)
+    return 0, ws
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(), 0),
+    (dict(T=0), -1), (dict(D=0), -1), (dict(L_min=0, L_max=0), -1),
+    (dict(L_min=4, L_max=3), -1), (dict(L_min=17, L_max=17), -1),
+    (dict(k=0), -1), (dict(k=65), -1), (dict(precision=3), -1), (dict(precision=-1), -1),
+    (dict(row_batch=128), -2), (dict(L_min=2, L_max=5), -2),
+    (dict(L_min=1, L_max=16, k=64), 0), (dict(L_min=16, L_max=16, k=64), 0),
+    # n' = T - L + 1 must leave k candidates beyond the exclusion zone
+    (dict(T=6, D=1, L_min=2, L_max=2, k=2), 0), (dict(T=6, D=1, L_min=2, L_max=2, k=3), -1),
+    (dict(T=9, D=4, L_min=1, L_max=1, k=8), 0), (dict(T=9, D=4, L_min=1, L_max=1, k=9), -1),
+])
+def test_plan_validation(kw, code):
+    assert _plan_code(**kw)[0] == code
+
+
+def test_plan_null_pointers():
+    lib = ctypes.CDLL(tk.LIB_PATH)
+    cfg = tk.traknn_config(512, 1024, 3, 3, 5, 1, 0)
+    h = ctypes.c_void_p()
+    ws = ctypes.c_size_t()
+    lib.traknn_plan.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    assert lib.traknn_plan(None, ctypes.byref(h), ctypes.byref(ws)) == -1
+    assert lib.traknn_plan(ctypes.byref(cfg), None, ctypes.byref(ws)) == -1
+    assert lib.traknn_plan(ctypes.byref(cfg), ctypes.byref(h), None) == -1
+    lib.traknn_plan_destroy.argtypes = [ctypes.c_void_p]
+    assert lib.traknn_plan_destroy(None) == -1
+
+
+def test_workspace_sizes():
+    # the distance matrix dominates: T * round_up(T, 64) * 4 bytes
+    _, ws_small = _plan_code()
+    _, ws_full = _plan_code(T=27394, D=8192, L_min=5, L_max=5, k=10)
+    assert ws_small > 512 * 512 * 4
+    assert ws_full >= 27394 * 27456 * 4 + 27648 * 8192 * 4
+    for prec in (0, 1, 2):
+        assert _plan_code(precision=prec)[0] == 0
+    _, ws_fp16 = _plan_code(T=27394, D=8192, L_min=5, L_max=5, k=10, precision=2)
+    assert ws_fp16 < ws_full
+
+
+class _FakeDev:
+    """An address-only stand-in: validation reads pointer values, never data."""
+
+    def __init__(self, addr):
+        self.addr = addr
+
+    def data_ptr(self):
+        return self.addr
+
+
+def test_knn_argument_validation_enqueues_nothing():
+    h, ws = tk.traknn_plan(512, 1024, 3, 3, 5, 1)
+    try:
+        X, W, I, Dd = (_FakeDev(0x100000), _FakeDev(0x200000), _FakeDev(0x300000),
+                       _FakeDev(0x400000))
+        cases = [
+            (dict(X=None), -1), (dict(ldx=1000), -1), (dict(ldx=1026), -1),
+            (dict(X=_FakeDev(0x100004)), -1), (dict(ws=None), -3),
+            (dict(ws=_FakeDev(0x200010)), -3), (dict(ws_bytes=ws - 1), -3),
+            (dict(nbr_idx=None), -1), (dict(nbr_dist=None), -1),
+        ]
+        for kw, code in cases:
+            a = dict(X=X, ldx=1024, ws=W, ws_bytes=ws, nbr_idx=I, nbr_dist=Dd)
+            a.update(kw)
+            with pytest.raises(tk.TraknnError) as e:
+                tk.traknn_knn(h, a["X"], a["ldx"], a["ws"], a["ws_bytes"], a["nbr_idx"],
+                              a["nbr_dist"], stream=0)
+            assert e.value.code == code, kw
+        with pytest.raises(tk.TraknnError) as e:
+            tk.traknn_score(h, None, Dd, stream=0)
+        assert e.value.code == -1
+        with pytest.raises(tk.TraknnError) as e:
+            tk.traknn_score_backward(h, X, 1024, I, None, W, 1024, W, ws, stream=0)
+        assert e.value.code == -1
+        with pytest.raises(tk.TraknnError) as e:
+            tk.traknn_score_backward(h, X, 1024, I, Dd, W, 1000, W, ws, stream=0)
+        assert e.value.code == -1
+        with pytest.raises(tk.TraknnError) as e:
+            tk.traknn_stage_times(h)
+        assert e.value.code == -2
+    finally:
+        tk.traknn_plan_destroy(h)
+
+
+def test_backward_needs_single_length():
+    h, ws = tk.traknn_plan(300, 16, 1, 4, 3, 0)
+    try:
+        with pytest.raises(tk.TraknnError) as e:
+            tk.traknn_score_backward(h, _FakeDev(0x1000), 16, _FakeDev(0x2000),
+                                     _FakeDev(0x3000), _FakeDev(0x4000), 16,
+                                     _FakeDev(0x10000), ws, stream=0)
+        assert e.value.code == -2
+    finally:
+        tk.traknn_plan_destroy(h)

@@ -1,0 +1,212 @@
+"""GPU parity of the HIP path against the FP64 oracle (small and ragged cases).
+
+Every call goes through the C ABI (``paper_2603_02059_amd.traknn``). Sizes are
+chosen so the oracle finishes in seconds while the kernels still see several
+256-row Gram tiles, ragged T and D tails, several 64-diagonal window chunks and
+several column splits.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2603_02059_amd import synth
+from tests.parity import check_rows, gram_norm_tol, precision_tol
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _tk():
+    from paper_2603_02059_amd import traknn as tk
+    return tk
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _run(Xn, L, k, prec, L_max=None):
+    tk = _tk()
+    X = torch.from_numpy(np.ascontiguousarray(Xn, dtype=np.float32)).cuda()
+    p = tk.Plan(X.shape[0], X.shape[1], L, L_max, k, prec)
+    idx, dist = p.knn(X)
+    s = p.score(dist)
+    torch.cuda.synchronize()
+    out = idx.cpu().numpy(), dist.cpu().numpy(), s.cpu().numpy()
+    p.close()
+    return out
+
+
+def _full_check(Xn, L, k, prec, tol=None, norm_tol=0.0):
+    tol = precision_tol(prec) if tol is None else tol
+    idx, dist, s = _run(Xn, L, k, prec)
+    n = Xn.shape[0] - L + 1
+    rows = np.arange(n)
+    ref = oracle.knn(Xn, L, k)
+    Dm = oracle.traj_dist(Xn, L)
+    stats = check_rows(Xn, L, k, rows, idx[0], dist[0], s[0], tol,
+                       ref=(ref[0], ref[1], ref[2], ref[3], Dm), norm_tol=norm_tol)
+    return stats
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "fp16"])
+def test_tiny_workload(prec):
+    w = synth.WORKLOADS["tiny"]
+    _say(f"[gpu] tiny workload T={w.T} D={w.D} L={w.L} k={w.k} prec={prec}")
+    Xn, starts = synth.make_workload(w)
+    stats = _full_check(Xn, w.L, w.k, prec)
+    _say(f"  {stats}")
+    idx, dist, s = _run(Xn, w.L, w.k, prec)
+    assert int(np.argmax(s[0])) == starts[0]
+
+
+@pytest.mark.parametrize("T,D,L,k,prec", [
+    (700, 1000, 4, 7, "bf16x3"),
+    (700, 1000, 1, 1, "fp32"),
+    (613, 77, 6, 3, "fp16"),
+    (300, 5, 2, 9, "bf16x3"),
+    (520, 300, 16, 64, "bf16x3"),
+])
+def test_ragged_shapes(T, D, L, k, prec):
+    _say(f"[gpu] ragged T={T} D={D} L={L} k={k} prec={prec}")
+    Xn, _ = synth.make_fields(T, 1, D, sigma=2.0, n_events=2, event_len=L, seed=T + D)
+    # off-workload shapes: workload tolerance plus the Gram's norm-relative floor
+    stats = _full_check(Xn, L, k, prec, norm_tol=gram_norm_tol(prec, D))
+    _say(f"  {stats}")
+
+
+def test_worked_example(golden_dir):
+    with open(os.path.join(golden_dir, "worked_example.json")) as f:
+        g = json.load(f)
+    x = np.array(g["x"], dtype=np.float32)[:, None]
+    # One cell, no averaging over cells: the centred values (up to ~9) are
+    # represented to 2^-24 (FP32), 2^-16 (BF16 hi+lo) and 2^-11 (FP16) relative,
+    # on differences as small as 3 -> relative distance bounds below.
+    for prec, tol in (("fp32", 1e-6), ("bf16x3", 5e-4), ("fp16", 2e-2)):
+        for case in g["cases"]:
+            _say(f"[gpu] worked example k={case['k']} prec={prec}")
+            idx, dist, s = _run(x, g["L"], case["k"], prec)
+            assert idx[0].tolist() == case["idx"]
+            np.testing.assert_allclose(dist[0], np.array(case["dist"], float), rtol=tol)
+            np.testing.assert_allclose(s[0], np.array(case["score"], float), rtol=tol)
+
+
+def test_constant_series_ties():
+    _say("[gpu] constant series")
+    Xn = np.full((300, 37), 101300.0, dtype=np.float32)
+    L, k = 3, 6
+    for prec in ("fp32", "bf16x3", "fp16"):
+        idx, dist, s = _run(Xn, L, k, prec)
+        ref_idx, _, _, _ = oracle.knn(Xn, L, k)
+        assert np.array_equal(idx[0], ref_idx)
+        assert np.all(dist[0] == 0) and np.all(s[0] == 0)
+
+
+def test_planted_trajectory_translation_and_scale():
+    """Adding a constant field changes nothing; doubling X quadruples scores."""
+    w = synth.WORKLOADS["tiny"]
+    _say("[gpu] translation / scaling invariance")
+    Xn, starts = synth.make_workload(w)
+    i0, d0, s0 = _run(Xn, w.L, w.k, "bf16x3")
+    i1, d1, s1 = _run(Xn - 101300.0, w.L, w.k, "bf16x3")
+    i2, d2, s2 = _run(2.0 * Xn, w.L, w.k, "bf16x3")
+    np.testing.assert_allclose(s1, s0, rtol=2e-5)
+    np.testing.assert_allclose(s2, 4.0 * s0, rtol=2e-5)
+    assert int(np.argmax(s1[0])) == int(np.argmax(s2[0])) == starts[0]
+
+
+def test_multi_length_sweep():
+    T, D, Lmax, k = 600, 200, 6, 5
+    _say(f"[gpu] sweep L=1..{Lmax} T={T} D={D}")
+    Xn, _ = synth.make_fields(T, 10, 20, sigma=2.0, n_events=3, event_len=4, seed=5)
+    idx, dist, s = _run(Xn, 1, k, "bf16x3", L_max=Lmax)
+    S = oracle.snapshot_dist(Xn)
+    for L in range(1, Lmax + 1):
+        n = T - L + 1
+        Dm = oracle.traj_dist_from_snapshot(S, L)
+        ref = oracle.knn_from_rows(Dm, np.arange(n), L, k)
+        stats = check_rows(Xn, L, k, np.arange(n), idx[L - 1, :n], dist[L - 1, :n],
+                           s[L - 1, :n], 1e-5, ref=ref + (Dm,),
+                           norm_tol=gram_norm_tol("bf16x3", 200))
+        _say(f"  L={L}: {stats}")
+        assert np.all(idx[L - 1, n:] == -1) and np.all(np.isinf(dist[L - 1, n:]))
+        assert np.all(np.isnan(s[L - 1, n:]))
+        # one pass over all lengths = separate single-length runs
+        i1, d1, s1 = _run(Xn, L, k, "bf16x3")
+        np.testing.assert_allclose(s[L - 1, :n], s1[0], rtol=1e-12)
+
+
+def test_determinism():
+    w = synth.WORKLOADS["tiny"]
+    _say("[gpu] determinism")
+    Xn, _ = synth.make_workload(w)
+    a = _run(Xn, w.L, w.k, "bf16x3")
+    b = _run(Xn, w.L, w.k, "bf16x3")
+    for u, v in zip(a, b):
+        assert np.array_equal(u, v)
+
+
+def _grad_case(Xn, L, k, prec, weights_fn):
+    tk = _tk()
+    X = torch.from_numpy(Xn).cuda().requires_grad_(True)
+    s, idx = tk.score(X, L, k, prec)
+    w = weights_fn(s.detach().cpu().numpy())
+    (s * torch.from_numpy(w).cuda()).sum().backward()
+    torch.cuda.synchronize()
+    return X.grad.cpu().numpy().astype(np.float64), idx.cpu().numpy(), w
+
+
+def test_backward_tiny():
+    w = synth.WORKLOADS["tiny"]
+    _say("[gpu] backward tiny, top-8 rarest")
+    Xn, _ = synth.make_workload(w)
+
+    def top8(s):
+        out = np.zeros_like(s)
+        out[np.argsort(-s, kind="stable")[:8]] = 1.0
+        return out
+
+    g, idx, wts = _grad_case(Xn, w.L, w.k, "bf16x3", top8)
+    g_ref = oracle.score_grad(Xn, w.L, w.k, idx, wts)
+    err = np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref)
+    _say(f"  normwise grad error {err:.3e}")
+    assert err < 1e-6
+    nz = np.abs(g_ref) > 1e-6 * np.abs(g_ref).max()
+    assert np.max(np.abs(g - g_ref)[nz] / np.abs(g_ref)[nz]) < 1e-5
+    assert np.all(g[~np.any(g_ref != 0, axis=1)] == 0)
+    # translation invariance and degree-2 homogeneity of F
+    np.testing.assert_allclose(g.sum(0), 0.0, atol=1e-6 * np.abs(g).max() * Xn.shape[0])
+
+
+def test_backward_all_weights_and_worked_example(golden_dir):
+    _say("[gpu] backward, random weights on every trajectory")
+    Xn, _ = synth.make_fields(200, 6, 7, sigma=1.5, seed=9)
+    rng = np.random.default_rng(3)
+    g, idx, wts = _grad_case(Xn, 3, 4, "fp32", lambda s: rng.uniform(-1, 1, s.shape))
+    g_ref = oracle.score_grad(Xn, 3, 4, idx, wts)
+    err = np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref)
+    assert err < 1e-6
+    with open(os.path.join(golden_dir, "worked_example.json")) as f:
+        gold = json.load(f)
+    x = np.array(gold["x"], dtype=np.float32)[:, None]
+    gc = gold["grad_case"]
+    g, idx, _ = _grad_case(x, gold["L"], gc["k"], "fp32",
+                           lambda s: np.array(gc["weights"], dtype=np.float64))
+    np.testing.assert_array_equal(g[:, 0], np.array(gc["grad"], dtype=np.float64))
+
+
+def test_stage_timing():
+    tk = _tk()
+    w = synth.WORKLOADS["tiny"]
+    Xn, _ = synth.make_workload(w)
+    X = torch.from_numpy(Xn).cuda()
+    p = tk.Plan(w.T, w.D, w.L, w.L, w.k, "bf16x3")
+    p.set_timing(True)
+    p.knn(X)
+    t = p.stage_times()
+    assert set(t) == set(tk.STAGES) and all(v >= 0 for v in t.values())
+    p.close()
