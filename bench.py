@@ -1,0 +1,253 @@
+"""Benchmark of the TRAKNN hot path on one MI355X.
+
+Workload: T = 27394 daily fields (75 years) of a 64 x 128 grid (D = 8192),
+trajectory length L = 5, k = 10 neighbours, synthetic SLP-shaped fields (see
+paper_2603_02059_amd/synth.py). One step = one whole pass of the hot path on
+device-resident X: centring/conversion, symmetric Gram + distances, window
+recurrence + exclusion-zone top-k, merge, scores.
+
+Metric: trajectory pairs per second, n'^2 / step time with n' = T - L + 1.
+The headline path is the split BF16x3 Gram; the plain FP32 and single-pass
+FP16 paths are timed beside it. One JSON line goes to stdout; progress to
+stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+PEAKS_TFLOPS = {"bf16x3": 2516.6, "fp16": 2516.6, "fp32": 157.3}  # dense MFMA
+HBM_PEAK_GBS = 8000.0
+GRAM_SOURCES = ("paper_2603_02059_amd/csrc/gram.hip",)
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gram_bf16x3_T27394_D8192_traffic.txt")
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def gram_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in GRAM_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic():
+    """HBM bytes per Gram launch from the committed rocprofv3 counter summary,
+    or None if absent or taken on a different Gram kernel source."""
+    try:
+        kv = {}
+        with open(TRAFFIC_FILE) as f:
+            for line in f:
+                if ":" in line and not line.startswith("#"):
+                    a, b = line.split(":", 1)
+                    kv[a.strip()] = b.strip()
+        if kv.get("gram_source_sha256_16") != gram_source_hash():
+            return None
+        return float(kv["hbm_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def gram_flops(T: int, D: int, prec: str) -> float:
+    """Algorithmic flops of one Gram launch: the T(T+1)/2 upper-triangle pairs
+    (diagonal included) times 2D, times the 3 products of the split path."""
+    passes = 3 if prec == "bf16x3" else 1
+    return passes * 2.0 * D * T * (T + 1) / 2.0
+
+
+def time_path(tk, torch, X, w, prec, steps, warmup):
+    p = tk.Plan(w.T, w.D, w.L, w.L, w.k, prec)
+    idx, dist = p.empty_outputs()
+    scores = torch.empty((1, p.np0), dtype=torch.float64, device=X.device)
+    for _ in range(warmup):
+        p.knn(X, idx, dist)
+        p.score(dist, scores)
+    torch.cuda.synchronize()
+    p.set_timing(True)
+    stage_ms = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        p.knn(X, idx, dist)
+        p.score(dist, scores)
+        stage_ms.append(p.stage_times())  # waits for this step's last stage event
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    p.set_timing(False)
+    out = {
+        "prec": prec,
+        "ms_per_step": 1e3 * total / steps,
+        "stage_ms": {k: float(np.mean([s[k] for s in stage_ms])) for k in stage_ms[0]},
+        "idx": idx[0],
+        "dist": dist[0],
+        "scores": scores[0],
+    }
+    p.close()
+    return out
+
+
+def cpu_baseline(Xn, w, budget_s, gidx, gdist, gscore):
+    """The FP64 oracle on evenly spaced sample rows, timed on the host cores,
+    plus the parity of the GPU rows against it."""
+    import oracle
+    from tests.parity import check_rows
+
+    n = w.T - w.L + 1
+    order = np.linspace(0, n - 1, 4096).astype(np.int64)
+    threads = oracle.num_threads()
+    done = []
+    res = []
+    t0 = time.perf_counter()
+    batch = 8
+    for b in range(0, len(order), batch):
+        rows = order[b:b + batch]
+        res.append(oracle.knn_rows(Xn, w.L, w.k, rows))
+        done.extend(rows.tolist())
+        if time.perf_counter() - t0 > budget_s:
+            break
+    el = time.perf_counter() - t0
+    rows = np.array(done, dtype=np.int64)
+    ref = tuple(np.concatenate([r[i] for r in res]) for i in range(5))
+    try:
+        par = check_rows(Xn, w.L, w.k, rows, gidx[rows], gdist[rows], gscore[rows], 1e-5,
+                         ref=ref)
+        par["pass"] = True
+    except AssertionError as e:  # reported, not hidden
+        par = {"pass": False, "rows": len(rows), "error": str(e)[:300]}
+    return {
+        "value": len(rows) * n / el,
+        "unit": "pairs/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"{len(rows)} evenly spaced rows x {n} candidates each of the same "
+                  f"workload (FP64 direct differences, direct L-sums, sorted top-k), "
+                  f"{el:.1f} s",
+    }, par
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="full")
+    ap.add_argument("--compare-steps", type=int, default=3,
+                    help="timed steps of the FP32 and FP16 comparison paths")
+    ap.add_argument("--cpu-budget", type=float, default=15.0,
+                    help="seconds of oracle time for the CPU baseline (0 = skip)")
+    ap.add_argument("--only", default=None, help="time one precision only")
+    ap.add_argument("--calibrate-copy-gib", type=float, default=0.0,
+                    help="also run a plain device copy of this many GiB (counter scale)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU: this build has no multi-GPU path "
+              "(see DESIGN.md for how the hot path would shard).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2603_02059_amd import synth
+    from paper_2603_02059_amd import traknn as tk
+
+    w = synth.WORKLOADS[args.workload]
+    t0 = time.perf_counter()
+    Xn, starts = synth.make_workload(w)
+    log(f"[bench] generated {w.name}: T={w.T} D={w.D} L={w.L} k={w.k} in "
+        f"{time.perf_counter() - t0:.1f}s")
+    X = torch.from_numpy(Xn).cuda()
+    torch.cuda.synchronize()
+
+    if args.calibrate_copy_gib > 0:
+        nb = int(args.calibrate_copy_gib * 2 ** 30) // 4
+        a = torch.ones(nb, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy of {4 * nb} bytes done")
+        del a, b
+
+    n = w.T - w.L + 1
+    pairs = float(n) * float(n)
+    precs = [args.only] if args.only else ["bf16x3", "fp32", "fp16"]
+    results = {}
+    for prec in precs:
+        steps = args.steps if prec == precs[0] else args.compare_steps
+        log(f"[bench] timing {prec}: {args.warmup} warmup + {steps} steps")
+        r = time_path(tk, torch, X, w, prec, steps, args.warmup)
+        r["pairs_per_s"] = pairs / (r["ms_per_step"] * 1e-3)
+        g = r["stage_ms"]["gram"]
+        r["gram_tflops"] = gram_flops(w.T, w.D, prec) / (g * 1e-3) / 1e12
+        r["gram_fp32_equiv_tflops"] = gram_flops(w.T, w.D, "fp32") / (g * 1e-3) / 1e12
+        log(f"[bench] {prec}: {r['ms_per_step']:.2f} ms/step, "
+            f"{r['pairs_per_s']:.3e} pairs/s, stages {r['stage_ms']}, "
+            f"gram {r['gram_tflops']:.1f} TFLOP/s")
+        results[prec] = r
+
+    head = results[precs[0]]
+    hp = head["prec"]
+    gidx = head["idx"].cpu().numpy()
+    gdist = head["dist"].cpu().numpy()
+    gscore = head["scores"].cpu().numpy()
+    rarest = np.argsort(-gscore, kind="stable")[:40]
+    planted_found = sum(1 for s in starts if s in set(rarest.tolist()))
+
+    cpu, par = None, None
+    if args.cpu_budget > 0:
+        log(f"[bench] oracle CPU baseline (~{args.cpu_budget:.0f}s) ...")
+        cpu, par = cpu_baseline(Xn, w, args.cpu_budget, gidx, gdist, gscore)
+        log(f"[bench] cpu baseline {cpu['value']:.3e} pairs/s on {cpu['cores']} threads; "
+            f"parity on {par['rows']} rows: {par}")
+
+    gram_ms = head["stage_ms"]["gram"]
+    achieved = gram_flops(w.T, w.D, hp) / (gram_ms * 1e-3) / 1e12
+    traffic = read_traffic() if hp == "bf16x3" and w.name == "full" else None
+    line = {
+        "metric": "trajectory pairs/sec at T=27394,D=8192,L=5,k=10; Gram MFMA util vs FP32 path",
+        "value": head["pairs_per_s"],
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16x3" if hp == "bf16x3" else hp,
+        "data": "synthetic SLP-shaped fields (seeded), device-resident",
+        "config": {"workload": f"{w.name}: T={w.T} daily fields, {w.H}x{w.W} grid (D={w.D}), "
+                               f"L={w.L}, k={w.k}, exclusion |i-j|<{w.L}, {w.n_events} planted "
+                               f"{w.event_len}-day dipoles",
+                   "T": w.T, "D": w.D, "L": w.L, "k": w.k, "precision": hp,
+                   "pairs_per_step": pairs},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAKS_TFLOPS[hp],
+                     "unit": "TFLOP/s", "frac": achieved / PEAKS_TFLOPS[hp],
+                     "traffic": traffic, "kernel": f"gram_kernel<{hp}>",
+                     "avg_launch_ms": gram_ms},
+        "cpu_baseline": cpu,
+        "stages_ms": {p: {k: round(v, 4) for k, v in r["stage_ms"].items()}
+                      for p, r in results.items()},
+        "paths": {p: {"ms_per_step": r["ms_per_step"], "pairs_per_s": r["pairs_per_s"],
+                      "gram_tflops": r["gram_tflops"],
+                      "gram_mfma_frac": r["gram_tflops"] / PEAKS_TFLOPS[p],
+                      "gram_fp32_equiv_tflops": r["gram_fp32_equiv_tflops"]}
+                  for p, r in results.items()},
+        "parity_sample": par,
+        "planted_in_top40": f"{planted_found}/{len(starts)}",
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()
