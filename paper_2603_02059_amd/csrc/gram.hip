@@ -31,6 +31,9 @@ constexpr int TILE = GRAM_TILE;
 constexpr int RB = GRAM_ROW_BYTES;          // bytes per row per stage
 constexpr int OPER_BYTES = TILE * RB;       // one operand tile in LDS (32 KB)
 constexpr int CHUNKS_PER_THREAD = TILE * (RB / 16) / GRAM_THREADS;  // 8
+constexpr int EPI_PITCH = 36;  // floats per parked accumulator column (32 + 4)
+static_assert(4 * 128 * EPI_PITCH * 4 + 2 * TILE * 8 <= GRAM_STAGES * 2 * TILE * RB,
+              "epilogue staging must fit in the operand LDS");
 
 __device__ __forceinline__ int swz(int row, int chunk) {
   return ((chunk ^ (row & 7)) << 4);
@@ -198,53 +201,88 @@ __global__ __launch_bounds__(GRAM_THREADS, 1) void gram_kernel(
     __syncthreads();
   }
 
-  // Epilogue: accumulator r of lane l in a 32x32 block holds
-  // row 8*(r/4) + 4*(l/32) + r%4, column l%32 of that block.
+  // Epilogue through LDS (the operand buffers are free now). Accumulator r of
+  // lane l in a 32x32 block holds row 8*(r/4) + 4*(l/32) + r%4, column l%32;
+  // each 32-row band (bm) of every wave is parked column-major in LDS with
+  // compile-time accumulator indices, then all 256 threads write the band's
+  // distances coalesced: rows of S for (i, j), and 128-byte runs of S rows for
+  // the mirrored (j, i).
+  float* stg = (float*)lds;                               // [4 waves][128][EP]
+  double* nI = (double*)(lds + 4 * 128 * EPI_PITCH * 4);  // [256]
+  double* nJ = nI + TILE;                                  // [256]
+  {
+    const int64_t gi = (int64_t)I * TILE + tid, gj = (int64_t)J * TILE + tid;
+    nI[tid] = gi < T ? norm[gi] : 0.0;
+    nJ[tid] = gj < T ? norm[gj] : 0.0;
+  }
   const bool diag = I == J;
+  const int64_t i_base = (int64_t)I * TILE, j_base = (int64_t)J * TILE;
 #pragma unroll
   for (int bm = 0; bm < 4; ++bm) {
+    float* mine = stg + w * 128 * EPI_PITCH;
 #pragma unroll
-    for (int bn = 0; bn < 4; ++bn) {
-      const int64_t j = (int64_t)J * TILE + wn * 128 + bn * 32 + (lane & 31);
-      const double nj = j < T ? norm[j] : 0.0;
+    for (int bn = 0; bn < 4; ++bn)
 #pragma unroll
-      for (int r4 = 0; r4 < 4; ++r4) {
-        const int64_t i0 = (int64_t)I * TILE + wm * 128 + bm * 32 + 8 * r4 + 4 * (lane >> 5);
-        float f[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int64_t i = i0 + e;
-          const double ni = i < T ? norm[i] : 0.0;
-          double v = ni + nj - 2.0 * (double)acc[bm][bn][4 * r4 + e];
-          f[e] = v > 0.0 ? (float)v : 0.f;
-        }
-        if (j >= T) continue;
-        if (!diag) {
-#pragma unroll
-          for (int e = 0; e < 4; ++e)
-            if (i0 + e < T) S[(i0 + e) * ldS + j] = f[e];
-          if (i0 + 3 < T) {
-            *(f32x4*)(S + j * ldS + i0) = f32x4{f[0], f[1], f[2], f[3]};
-          } else {
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-              if (i0 + e < T) S[j * ldS + i0 + e] = f[e];
-          }
-        } else {
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const int64_t i = i0 + e;
-            if (i >= T) continue;
-            if (i < j) {
-              S[i * ldS + j] = f[e];
-              S[j * ldS + i] = f[e];
-            } else if (i == j) {
-              S[i * ldS + i] = 0.f;
-            }
+      for (int q = 0; q < 4; ++q) {
+        const int col = bn * 32 + (lane & 31);
+        const int row = 8 * q + 4 * (lane >> 5);
+        *(f32x4*)(mine + col * EPI_PITCH + row) =
+            f32x4{acc[bm][bn][4 * q + 0], acc[bm][bn][4 * q + 1],
+                  acc[bm][bn][4 * q + 2], acc[bm][bn][4 * q + 3]};
+      }
+    __syncthreads();
+    // (i, j): thread tid owns tile column jl = tid; rows wm*128 + bm*32 + r
+    {
+      const int jl = tid;
+      const int wn_ = jl >> 7, c = jl & 127;
+      const int64_t j = j_base + jl;
+      const double nj = nJ[jl];
+      if (j < T) {
+        for (int wm_ = 0; wm_ < 2; ++wm_) {
+          const float* src = stg + (wm_ * 2 + wn_) * 128 * EPI_PITCH + c * EPI_PITCH;
+          for (int r = 0; r < 32; ++r) {
+            const int il = wm_ * 128 + bm * 32 + r;
+            const int64_t i = i_base + il;
+            if (i >= T) break;
+            if (diag && il >= jl) continue;  // diagonal tile: strict upper half
+            const double v = nI[il] + nj - 2.0 * (double)src[r];
+            S[i * ldS + j] = v > 0.0 ? (float)v : 0.f;
           }
         }
       }
     }
+    // (j, i): 8 threads per (column, row half) write 32 consecutive i
+    for (int run = tid >> 3; run < 2 * TILE; run += GRAM_THREADS / 8) {
+      const int jl = run >> 1, wm_ = run & 1;
+      const int wn_ = jl >> 7, c = jl & 127;
+      const int64_t j = j_base + jl;
+      if (j >= T) continue;
+      const int q = tid & 7;
+      const int il0 = wm_ * 128 + bm * 32 + 4 * q;
+      const int64_t i0 = i_base + il0;
+      const f32x4 g = *(const f32x4*)(stg + (wm_ * 2 + wn_) * 128 * EPI_PITCH +
+                                       c * EPI_PITCH + 4 * q);
+      const double nj = nJ[jl];
+      float f[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const double v = nI[il0 + e] + nj - 2.0 * (double)g[e];
+        f[e] = v > 0.0 ? (float)v : 0.f;
+      }
+      float* dst = S + j * ldS + i0;
+      if (!diag && i0 + 3 < T) {
+        *(f32x4*)dst = f32x4{f[0], f[1], f[2], f[3]};
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int il = il0 + e;
+          if (i0 + e >= T) continue;
+          if (!diag || il < jl) dst[e] = f[e];
+          else if (il == jl) dst[e] = 0.f;
+        }
+      }
+    }
+    __syncthreads();
   }
 }
 
