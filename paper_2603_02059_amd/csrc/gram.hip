@@ -25,18 +25,24 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
-typedef int i32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int TILE = GRAM_TILE;
 constexpr int RB = GRAM_ROW_BYTES;          // bytes per row per stage
 constexpr int OPER_BYTES = TILE * RB;       // one operand tile in LDS (32 KB)
-constexpr int CHUNKS_PER_THREAD = TILE * (RB / 16) / GRAM_THREADS;  // 8
+// s_waitcnt immediate waiting for vmcnt == 0 only (expcnt, lgkmcnt at max)
+constexpr int VMCNT0 = 0x0F70;
 constexpr int EPI_PITCH = 36;  // floats per parked accumulator column (32 + 4)
 static_assert(4 * 128 * EPI_PITCH * 4 + 2 * TILE * 8 <= GRAM_STAGES * 2 * TILE * RB,
               "epilogue staging must fit in the operand LDS");
 
+// Physical 16-byte slot of logical chunk `chunk` in LDS row `row`. The XOR key
+// (row ^ row>>3) & 7 makes any 8 aligned consecutive rows use 8 distinct
+// slots and any 16 aligned consecutive rows use 16 distinct (row parity,
+// slot) pairs, so ds_read_b128 of 32 consecutive rows is conflict-free
+// whether the LDS serves 8 lanes over 32 banks or 16 lanes over 64 banks.
+__device__ __forceinline__ int swz_key(int row) { return (row ^ (row >> 3)) & 7; }
 __device__ __forceinline__ int swz(int row, int chunk) {
-  return ((chunk ^ (row & 7)) << 4);
+  return ((chunk ^ swz_key(row)) << 4);
 }
 
 // Tile id -> (I, J), I <= J, in the XCD-aware grouped order described above.
@@ -69,6 +75,14 @@ __device__ __forceinline__ bool decode_tile(int64_t wg, int nb, int64_t ntiles,
   return false;
 }
 
+// Scheduling-group masks for __builtin_amdgcn_sched_group_barrier.
+constexpr int SG_MFMA = 0x008;
+constexpr int SG_DS_READ = 0x100;
+
+// One K stage of MFMAs on the LDS operand tiles A (rows of the I block) and B
+// (rows of the J block). Fragments of the first k-slice are read up front; the
+// reads of each later slice are interleaved with the MFMAs of the previous one
+// so only the first slice's LDS latency is exposed.
 template <int PREC>
 __device__ __forceinline__ void compute_stage(const char* __restrict__ A,
                                               const char* __restrict__ B,
@@ -77,68 +91,101 @@ __device__ __forceinline__ void compute_stage(const char* __restrict__ A,
   const int r32 = lane & 31;
   const int half = lane >> 5;
   if constexpr (PREC == TRAKNN_BF16X3) {
+    bf16x8 ah[2][4], al[2][4], bh[2][4], bl[2][4];
 #pragma unroll
     for (int kk = 0; kk < 2; ++kk) {
       const int g = 2 * kk + half;  // 8-element group this lane supplies
-      bf16x8 ah[4], al[4], bh[4], bl[4];
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
         const int ra = wm * 128 + b * 32 + r32;
         const int rb = wn * 128 + b * 32 + r32;
-        ah[b] = *(const bf16x8*)(A + ra * RB + swz(ra, 2 * g));
-        al[b] = *(const bf16x8*)(A + ra * RB + swz(ra, 2 * g + 1));
-        bh[b] = *(const bf16x8*)(B + rb * RB + swz(rb, 2 * g));
-        bl[b] = *(const bf16x8*)(B + rb * RB + swz(rb, 2 * g + 1));
+        ah[kk][b] = *(const bf16x8*)(A + ra * RB + swz(ra, 2 * g));
+        bh[kk][b] = *(const bf16x8*)(B + rb * RB + swz(rb, 2 * g));
+        al[kk][b] = *(const bf16x8*)(A + ra * RB + swz(ra, 2 * g + 1));
+        bl[kk][b] = *(const bf16x8*)(B + rb * RB + swz(rb, 2 * g + 1));
       }
+    }
+#pragma unroll
+    for (int kk = 0; kk < 2; ++kk)
 #pragma unroll
       for (int bm = 0; bm < 4; ++bm)
 #pragma unroll
         for (int bn = 0; bn < 4; ++bn) {
-          acc[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[bm], bh[bn], acc[bm][bn], 0, 0, 0);
-          acc[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[bm], bl[bn], acc[bm][bn], 0, 0, 0);
-          acc[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[bm], bh[bn], acc[bm][bn], 0, 0, 0);
+          acc[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[kk][bm], bh[kk][bn], acc[bm][bn], 0, 0, 0);
+          acc[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[kk][bm], bl[kk][bn], acc[bm][bn], 0, 0, 0);
+          acc[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[kk][bm], bh[kk][bn], acc[bm][bn], 0, 0, 0);
         }
+    // 16 reads | (3 MFMA, 1 read) x 16 | 48 MFMA
+#pragma unroll
+    for (int i = 0; i < 16; ++i) __builtin_amdgcn_sched_group_barrier(SG_DS_READ, 1, 0);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      __builtin_amdgcn_sched_group_barrier(SG_MFMA, 3, 0);
+      __builtin_amdgcn_sched_group_barrier(SG_DS_READ, 1, 0);
     }
+    __builtin_amdgcn_sched_group_barrier(SG_MFMA, 48, 0);
   } else if constexpr (PREC == TRAKNN_FP16) {
+    f16x8 a[4][4], b[4][4];
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
       const int g = 2 * kk + half;
-      f16x8 a[4], b[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int ra = wm * 128 + q * 32 + r32;
         const int rb = wn * 128 + q * 32 + r32;
-        a[q] = *(const f16x8*)(A + ra * RB + swz(ra, g));
-        b[q] = *(const f16x8*)(B + rb * RB + swz(rb, g));
+        a[kk][q] = *(const f16x8*)(A + ra * RB + swz(ra, g));
+        b[kk][q] = *(const f16x8*)(B + rb * RB + swz(rb, g));
       }
+    }
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk)
 #pragma unroll
       for (int bm = 0; bm < 4; ++bm)
 #pragma unroll
         for (int bn = 0; bn < 4; ++bn)
-          acc[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a[bm], b[bn], acc[bm][bn], 0, 0, 0);
+          acc[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a[kk][bm], b[kk][bn], acc[bm][bn], 0, 0, 0);
+    // 8 reads | ((2 MFMA, 1 read) x 8) x 3 | 16 MFMA
+#pragma unroll
+    for (int i = 0; i < 8; ++i) __builtin_amdgcn_sched_group_barrier(SG_DS_READ, 1, 0);
+#pragma unroll
+    for (int i = 0; i < 24; ++i) {
+      __builtin_amdgcn_sched_group_barrier(SG_MFMA, 2, 0);
+      __builtin_amdgcn_sched_group_barrier(SG_DS_READ, 1, 0);
     }
+    __builtin_amdgcn_sched_group_barrier(SG_MFMA, 16, 0);
   } else {
     // FP32: each lane reads 4 consecutive k of chunk 2s + half; MFMA e of the
     // four consumes element e, so the 4 MFMAs x 2 lane halves cover 8 k.
+    f32x4 a[4][4], b[4][4];
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const int c = 2 * s + half;
-      f32x4 a[4], b[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int ra = wm * 128 + q * 32 + r32;
         const int rb = wn * 128 + q * 32 + r32;
-        a[q] = *(const f32x4*)(A + ra * RB + swz(ra, c));
-        b[q] = *(const f32x4*)(B + rb * RB + swz(rb, c));
+        a[s][q] = *(const f32x4*)(A + ra * RB + swz(ra, c));
+        b[s][q] = *(const f32x4*)(B + rb * RB + swz(rb, c));
       }
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
 #pragma unroll
       for (int e = 0; e < 4; ++e)
 #pragma unroll
         for (int bm = 0; bm < 4; ++bm)
 #pragma unroll
           for (int bn = 0; bn < 4; ++bn)
-            acc[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[bm][e], b[bn][e], acc[bm][bn], 0, 0, 0);
+            acc[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[s][bm][e], b[s][bn][e], acc[bm][bn], 0, 0, 0);
+    // 8 reads | ((8 MFMA, 1 read) x 8) x 3 | 64 MFMA
+#pragma unroll
+    for (int i = 0; i < 8; ++i) __builtin_amdgcn_sched_group_barrier(SG_DS_READ, 1, 0);
+#pragma unroll
+    for (int i = 0; i < 24; ++i) {
+      __builtin_amdgcn_sched_group_barrier(SG_MFMA, 8, 0);
+      __builtin_amdgcn_sched_group_barrier(SG_DS_READ, 1, 0);
     }
+    __builtin_amdgcn_sched_group_barrier(SG_MFMA, 64, 0);
   }
 }
 
@@ -157,26 +204,20 @@ __global__ __launch_bounds__(GRAM_THREADS, 1) void gram_kernel(
   const char* Ag = xc + (int64_t)I * TILE * pitch;
   const char* Bg = xc + (int64_t)J * TILE * pitch;
 
-  i32x4 ra[CHUNKS_PER_THREAD], rb[CHUNKS_PER_THREAD];
-  auto gload = [&](int st) {
-#pragma unroll
-    for (int u = 0; u < CHUNKS_PER_THREAD; ++u) {
-      const int q = tid + GRAM_THREADS * u;
-      const int row = q >> 3, c = q & 7;
-      const int64_t off = (int64_t)row * pitch + (int64_t)st * RB + c * 16;
-      ra[u] = *(const i32x4*)(Ag + off);
-      rb[u] = *(const i32x4*)(Bg + off);
-    }
-  };
-  auto lstore = [&](int buf) {
+  // Direct global -> LDS loads (gfx950 global_load_lds_dwordx4): lane q of a
+  // load lands at byte 16*q of the wave's 1 KB destination block, so each lane
+  // fetches the logical chunk whose swizzled slot is that destination. Each
+  // wave moves 8 KB of A and 8 KB of B per stage and no VGPR stages the data.
+  auto issue = [&](int st, int buf) {
     char* A = lds + buf * 2 * OPER_BYTES;
-    char* B = A + OPER_BYTES;
 #pragma unroll
-    for (int u = 0; u < CHUNKS_PER_THREAD; ++u) {
-      const int q = tid + GRAM_THREADS * u;
-      const int row = q >> 3, c = q & 7;
-      *(i32x4*)(A + row * RB + swz(row, c)) = ra[u];
-      *(i32x4*)(B + row * RB + swz(row, c)) = rb[u];
+    for (int u = 0; u < OPER_BYTES / 1024 / 4; ++u) {
+      const int blk = w * (OPER_BYTES / 1024 / 4) + u;    // 1 KB block
+      const int row = blk * 8 + (lane >> 3);
+      const int c = (lane & 7) ^ swz_key(row);  // inverse of swz
+      const int64_t off = (int64_t)row * pitch + (int64_t)st * RB + c * 16;
+      __builtin_amdgcn_global_load_lds(Ag + off, A + blk * 1024, 16, 0, 0);
+      __builtin_amdgcn_global_load_lds(Bg + off, A + OPER_BYTES + blk * 1024, 16, 0, 0);
     }
   };
 
@@ -188,16 +229,16 @@ __global__ __launch_bounds__(GRAM_THREADS, 1) void gram_kernel(
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.f;
 
-  gload(0);
-  lstore(0);
+  issue(0, 0);
+  __builtin_amdgcn_s_waitcnt(VMCNT0);
   __syncthreads();
   for (int st = 0; st < nstages; ++st) {
     const int buf = st & 1;
     const bool more = st + 1 < nstages;
-    if (more) gload(st + 1);
+    if (more) issue(st + 1, buf ^ 1);
     const char* A = lds + buf * 2 * OPER_BYTES;
     compute_stage<PREC>(A, A + OPER_BYTES, wm, wn, lane, acc);
-    if (more) lstore(buf ^ 1);
+    if (more) __builtin_amdgcn_s_waitcnt(VMCNT0);
     __syncthreads();
   }
 
