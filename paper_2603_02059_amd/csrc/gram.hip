@@ -29,10 +29,18 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 constexpr int TILE = GRAM_TILE;
 constexpr int RB = GRAM_ROW_BYTES;          // bytes per row per stage
 constexpr int OPER_BYTES = TILE * RB;       // one operand tile in LDS (32 KB)
+// Wave grid of a workgroup: WAVES_M x WAVES_N waves, each owning a
+// WT_M x WT_N block of the 256 x 256 tile in 32x32 MFMA blocks.
+constexpr int WAVES_M = 2;
+constexpr int WAVES_N = GRAM_THREADS / 64 / WAVES_M;
+constexpr int WT_M = TILE / WAVES_M, WT_N = TILE / WAVES_N;
+constexpr int BM = WT_M / 32, BN = WT_N / 32;  // MFMA blocks per wave
+static_assert(WT_M == 128, "the epilogue parks 32-row bands of 128-row wave tiles");
 // s_waitcnt immediate waiting for vmcnt == 0 only (expcnt, lgkmcnt at max)
 constexpr int VMCNT0 = 0x0F70;
 constexpr int EPI_PITCH = 36;  // floats per parked accumulator column (32 + 4)
-static_assert(4 * 128 * EPI_PITCH * 4 + 2 * TILE * 8 <= GRAM_STAGES * 2 * TILE * RB,
+static_assert((GRAM_THREADS / 64) * (TILE / (GRAM_THREADS / 64 / 2)) * EPI_PITCH * 4 +
+                  2 * TILE * 8 <= GRAM_STAGES * 2 * TILE * RB,
               "epilogue staging must fit in the operand LDS");
 
 // Physical 16-byte slot of logical chunk `chunk` in LDS row `row`. The XOR key
@@ -79,92 +87,93 @@ __device__ __forceinline__ bool decode_tile(int64_t wg, int nb, int64_t ntiles,
 constexpr int SG_MFMA = 0x008;
 constexpr int SG_DS_READ = 0x100;
 
+// Read/MFMA counts per k-slice and slices per stage for each precision.
+template <int PREC>
+struct SliceShape {
+  static constexpr int slices = PREC == TRAKNN_BF16X3 ? 2 : 4;
+  static constexpr int reads = PREC == TRAKNN_BF16X3 ? 2 * (BM + BN) : (BM + BN);
+  static constexpr int mfmas = PREC == TRAKNN_BF16X3 ? 3 * BM * BN
+                               : PREC == TRAKNN_FP16 ? BM * BN : 4 * BM * BN;
+};
+
 // One K stage of MFMAs on the LDS operand tiles A (rows of the I block) and B
-// (rows of the J block). Fragments of the first k-slice are read up front; the
-// reads of each later slice are interleaved with the MFMAs of the previous one
-// so only the first slice's LDS latency is exposed.
+// (rows of the J block). The first k-slice's fragments are read up front; the
+// reads of each later slice are spread over the MFMAs of the earlier slices so
+// only the first slice's LDS latency is exposed.
 template <int PREC>
 __device__ __forceinline__ void compute_stage(const char* __restrict__ A,
                                               const char* __restrict__ B,
                                               int wm, int wn, int lane,
-                                              f32x16 (&acc)[4][4]) {
+                                              f32x16 (&acc)[BM][BN]) {
+  using SS = SliceShape<PREC>;
   const int r32 = lane & 31;
   const int half = lane >> 5;
   if constexpr (PREC == TRAKNN_BF16X3) {
-    bf16x8 ah[2][4], al[2][4], bh[2][4], bl[2][4];
+    bf16x8 ah[2][BM], al[2][BM], bh[2][BN], bl[2][BN];
 #pragma unroll
     for (int kk = 0; kk < 2; ++kk) {
       const int g = 2 * kk + half;  // 8-element group this lane supplies
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const int ra = wm * 128 + b * 32 + r32;
-        const int rb = wn * 128 + b * 32 + r32;
-        ah[kk][b] = *(const bf16x8*)(A + ra * RB + swz(ra, 2 * g));
-        bh[kk][b] = *(const bf16x8*)(B + rb * RB + swz(rb, 2 * g));
-        al[kk][b] = *(const bf16x8*)(A + ra * RB + swz(ra, 2 * g + 1));
-        bl[kk][b] = *(const bf16x8*)(B + rb * RB + swz(rb, 2 * g + 1));
+      for (int q = 0; q < BM; ++q) {
+        const int ra = wm * WT_M + q * 32 + r32;
+        ah[kk][q] = *(const bf16x8*)(A + ra * RB + swz(ra, 2 * g));
+        al[kk][q] = *(const bf16x8*)(A + ra * RB + swz(ra, 2 * g + 1));
+      }
+#pragma unroll
+      for (int q = 0; q < BN; ++q) {
+        const int rb = wn * WT_N + q * 32 + r32;
+        bh[kk][q] = *(const bf16x8*)(B + rb * RB + swz(rb, 2 * g));
+        bl[kk][q] = *(const bf16x8*)(B + rb * RB + swz(rb, 2 * g + 1));
       }
     }
 #pragma unroll
     for (int kk = 0; kk < 2; ++kk)
 #pragma unroll
-      for (int bm = 0; bm < 4; ++bm)
+      for (int bm = 0; bm < BM; ++bm)
 #pragma unroll
-        for (int bn = 0; bn < 4; ++bn) {
+        for (int bn = 0; bn < BN; ++bn) {
           acc[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[kk][bm], bh[kk][bn], acc[bm][bn], 0, 0, 0);
           acc[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[kk][bm], bl[kk][bn], acc[bm][bn], 0, 0, 0);
           acc[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[kk][bm], bh[kk][bn], acc[bm][bn], 0, 0, 0);
         }
-    // 16 reads | (3 MFMA, 1 read) x 16 | 48 MFMA
-#pragma unroll
-    for (int i = 0; i < 16; ++i) __builtin_amdgcn_sched_group_barrier(SG_DS_READ, 1, 0);
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      __builtin_amdgcn_sched_group_barrier(SG_MFMA, 3, 0);
-      __builtin_amdgcn_sched_group_barrier(SG_DS_READ, 1, 0);
-    }
-    __builtin_amdgcn_sched_group_barrier(SG_MFMA, 48, 0);
   } else if constexpr (PREC == TRAKNN_FP16) {
-    f16x8 a[4][4], b[4][4];
+    f16x8 a[4][BM], b[4][BN];
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
       const int g = 2 * kk + half;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int ra = wm * 128 + q * 32 + r32;
-        const int rb = wn * 128 + q * 32 + r32;
+      for (int q = 0; q < BM; ++q) {
+        const int ra = wm * WT_M + q * 32 + r32;
         a[kk][q] = *(const f16x8*)(A + ra * RB + swz(ra, g));
+      }
+#pragma unroll
+      for (int q = 0; q < BN; ++q) {
+        const int rb = wn * WT_N + q * 32 + r32;
         b[kk][q] = *(const f16x8*)(B + rb * RB + swz(rb, g));
       }
     }
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk)
 #pragma unroll
-      for (int bm = 0; bm < 4; ++bm)
+      for (int bm = 0; bm < BM; ++bm)
 #pragma unroll
-        for (int bn = 0; bn < 4; ++bn)
+        for (int bn = 0; bn < BN; ++bn)
           acc[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a[kk][bm], b[kk][bn], acc[bm][bn], 0, 0, 0);
-    // 8 reads | ((2 MFMA, 1 read) x 8) x 3 | 16 MFMA
-#pragma unroll
-    for (int i = 0; i < 8; ++i) __builtin_amdgcn_sched_group_barrier(SG_DS_READ, 1, 0);
-#pragma unroll
-    for (int i = 0; i < 24; ++i) {
-      __builtin_amdgcn_sched_group_barrier(SG_MFMA, 2, 0);
-      __builtin_amdgcn_sched_group_barrier(SG_DS_READ, 1, 0);
-    }
-    __builtin_amdgcn_sched_group_barrier(SG_MFMA, 16, 0);
   } else {
     // FP32: each lane reads 4 consecutive k of chunk 2s + half; MFMA e of the
     // four consumes element e, so the 4 MFMAs x 2 lane halves cover 8 k.
-    f32x4 a[4][4], b[4][4];
+    f32x4 a[4][BM], b[4][BN];
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const int c = 2 * s + half;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int ra = wm * 128 + q * 32 + r32;
-        const int rb = wn * 128 + q * 32 + r32;
+      for (int q = 0; q < BM; ++q) {
+        const int ra = wm * WT_M + q * 32 + r32;
         a[s][q] = *(const f32x4*)(A + ra * RB + swz(ra, c));
+      }
+#pragma unroll
+      for (int q = 0; q < BN; ++q) {
+        const int rb = wn * WT_N + q * 32 + r32;
         b[s][q] = *(const f32x4*)(B + rb * RB + swz(rb, c));
       }
     }
@@ -173,20 +182,22 @@ __device__ __forceinline__ void compute_stage(const char* __restrict__ A,
 #pragma unroll
       for (int e = 0; e < 4; ++e)
 #pragma unroll
-        for (int bm = 0; bm < 4; ++bm)
+        for (int bm = 0; bm < BM; ++bm)
 #pragma unroll
-          for (int bn = 0; bn < 4; ++bn)
+          for (int bn = 0; bn < BN; ++bn)
             acc[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[s][bm][e], b[s][bn][e], acc[bm][bn], 0, 0, 0);
-    // 8 reads | ((8 MFMA, 1 read) x 8) x 3 | 64 MFMA
-#pragma unroll
-    for (int i = 0; i < 8; ++i) __builtin_amdgcn_sched_group_barrier(SG_DS_READ, 1, 0);
-#pragma unroll
-    for (int i = 0; i < 24; ++i) {
-      __builtin_amdgcn_sched_group_barrier(SG_MFMA, 8, 0);
-      __builtin_amdgcn_sched_group_barrier(SG_DS_READ, 1, 0);
-    }
-    __builtin_amdgcn_sched_group_barrier(SG_MFMA, 64, 0);
   }
+  // first slice's reads | (q MFMA, 1 read) for every later read | the rest
+  constexpr int later_reads = (SS::slices - 1) * SS::reads;
+  constexpr int q = SS::mfmas / SS::reads;
+#pragma unroll
+  for (int i = 0; i < SS::reads; ++i) __builtin_amdgcn_sched_group_barrier(SG_DS_READ, 1, 0);
+#pragma unroll
+  for (int i = 0; i < later_reads; ++i) {
+    __builtin_amdgcn_sched_group_barrier(SG_MFMA, q, 0);
+    __builtin_amdgcn_sched_group_barrier(SG_DS_READ, 1, 0);
+  }
+  __builtin_amdgcn_sched_group_barrier(SG_MFMA, SS::slices * SS::mfmas - later_reads * q, 0);
 }
 
 template <int PREC>
@@ -200,7 +211,7 @@ __global__ __launch_bounds__(GRAM_THREADS, 1) void gram_kernel(
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6;
-  const int wm = w >> 1, wn = w & 1;
+  const int wm = w / WAVES_N, wn = w % WAVES_N;
   const char* Ag = xc + (int64_t)I * TILE * pitch;
   const char* Bg = xc + (int64_t)J * TILE * pitch;
 
@@ -208,11 +219,12 @@ __global__ __launch_bounds__(GRAM_THREADS, 1) void gram_kernel(
   // load lands at byte 16*q of the wave's 1 KB destination block, so each lane
   // fetches the logical chunk whose swizzled slot is that destination. Each
   // wave moves 8 KB of A and 8 KB of B per stage and no VGPR stages the data.
+  constexpr int BLK_PER_WAVE = OPER_BYTES / 1024 / (GRAM_THREADS / 64);
   auto issue = [&](int st, int buf) {
     char* A = lds + buf * 2 * OPER_BYTES;
 #pragma unroll
-    for (int u = 0; u < OPER_BYTES / 1024 / 4; ++u) {
-      const int blk = w * (OPER_BYTES / 1024 / 4) + u;    // 1 KB block
+    for (int u = 0; u < BLK_PER_WAVE; ++u) {
+      const int blk = w * BLK_PER_WAVE + u;    // 1 KB block
       const int row = blk * 8 + (lane >> 3);
       const int c = (lane & 7) ^ swz_key(row);  // inverse of swz
       const int64_t off = (int64_t)row * pitch + (int64_t)st * RB + c * 16;
@@ -221,11 +233,11 @@ __global__ __launch_bounds__(GRAM_THREADS, 1) void gram_kernel(
     }
   };
 
-  f32x16 acc[4][4];
+  f32x16 acc[BM][BN];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < BM; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+    for (int b = 0; b < BN; ++b)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.f;
 
@@ -245,13 +257,14 @@ __global__ __launch_bounds__(GRAM_THREADS, 1) void gram_kernel(
   // Epilogue through LDS (the operand buffers are free now). Accumulator r of
   // lane l in a 32x32 block holds row 8*(r/4) + 4*(l/32) + r%4, column l%32;
   // each 32-row band (bm) of every wave is parked column-major in LDS with
-  // compile-time accumulator indices, then all 256 threads write the band's
+  // compile-time accumulator indices, then all threads write the band's
   // distances coalesced: rows of S for (i, j), and 128-byte runs of S rows for
   // the mirrored (j, i).
-  float* stg = (float*)lds;                               // [4 waves][128][EP]
-  double* nI = (double*)(lds + 4 * 128 * EPI_PITCH * 4);  // [256]
-  double* nJ = nI + TILE;                                  // [256]
-  {
+  constexpr int NWAVES = GRAM_THREADS / 64;
+  float* stg = (float*)lds;  // [NWAVES][WT_N][EPI_PITCH]
+  double* nI = (double*)(lds + NWAVES * WT_N * EPI_PITCH * 4);  // [256]
+  double* nJ = nI + TILE;                                        // [256]
+  if (tid < TILE) {
     const int64_t gi = (int64_t)I * TILE + tid, gj = (int64_t)J * TILE + tid;
     nI[tid] = gi < T ? norm[gi] : 0.0;
     nJ[tid] = gj < T ? norm[gj] : 0.0;
@@ -259,10 +272,10 @@ __global__ __launch_bounds__(GRAM_THREADS, 1) void gram_kernel(
   const bool diag = I == J;
   const int64_t i_base = (int64_t)I * TILE, j_base = (int64_t)J * TILE;
 #pragma unroll
-  for (int bm = 0; bm < 4; ++bm) {
-    float* mine = stg + w * 128 * EPI_PITCH;
+  for (int bm = 0; bm < BM; ++bm) {
+    float* mine = stg + w * WT_N * EPI_PITCH;
 #pragma unroll
-    for (int bn = 0; bn < 4; ++bn)
+    for (int bn = 0; bn < BN; ++bn)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int col = bn * 32 + (lane & 31);
@@ -272,15 +285,16 @@ __global__ __launch_bounds__(GRAM_THREADS, 1) void gram_kernel(
                   acc[bm][bn][4 * q + 2], acc[bm][bn][4 * q + 3]};
       }
     __syncthreads();
-    // (i, j): thread tid owns tile column jl = tid; rows wm*128 + bm*32 + r
+    // (i, j): thread tid owns tile column jl = tid % 256 and the row halves
+    // wm_ = tid / 256 (+ steps); rows wm_*128 + bm*32 + r
     {
-      const int jl = tid;
-      const int wn_ = jl >> 7, c = jl & 127;
+      const int jl = tid & (TILE - 1);
+      const int wn_ = jl / WT_N, c = jl % WT_N;
       const int64_t j = j_base + jl;
       const double nj = nJ[jl];
       if (j < T) {
-        for (int wm_ = 0; wm_ < 2; ++wm_) {
-          const float* src = stg + (wm_ * 2 + wn_) * 128 * EPI_PITCH + c * EPI_PITCH;
+        for (int wm_ = tid / TILE; wm_ < WAVES_M; wm_ += GRAM_THREADS / TILE) {
+          const float* src = stg + (wm_ * WAVES_N + wn_) * WT_N * EPI_PITCH + c * EPI_PITCH;
           for (int r = 0; r < 32; ++r) {
             const int il = wm_ * 128 + bm * 32 + r;
             const int64_t i = i_base + il;
@@ -293,15 +307,15 @@ __global__ __launch_bounds__(GRAM_THREADS, 1) void gram_kernel(
       }
     }
     // (j, i): 8 threads per (column, row half) write 32 consecutive i
-    for (int run = tid >> 3; run < 2 * TILE; run += GRAM_THREADS / 8) {
-      const int jl = run >> 1, wm_ = run & 1;
-      const int wn_ = jl >> 7, c = jl & 127;
+    for (int run = tid >> 3; run < WAVES_M * TILE; run += GRAM_THREADS / 8) {
+      const int jl = run / WAVES_M, wm_ = run % WAVES_M;
+      const int wn_ = jl / WT_N, c = jl % WT_N;
       const int64_t j = j_base + jl;
       if (j >= T) continue;
       const int q = tid & 7;
       const int il0 = wm_ * 128 + bm * 32 + 4 * q;
       const int64_t i0 = i_base + il0;
-      const f32x4 g = *(const f32x4*)(stg + (wm_ * 2 + wn_) * 128 * EPI_PITCH +
+      const f32x4 g = *(const f32x4*)(stg + (wm_ * WAVES_N + wn_) * WT_N * EPI_PITCH +
                                        c * EPI_PITCH + 4 * q);
       const double nj = nJ[jl];
       float f[4];

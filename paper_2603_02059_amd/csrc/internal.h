@@ -16,7 +16,7 @@ namespace traknn {
 // 2 * GRAM_TILE operand rows through LDS.
 // ---------------------------------------------------------------------------
 constexpr int GRAM_TILE = 256;
-constexpr int GRAM_THREADS = 256;
+constexpr int GRAM_THREADS = 512;
 constexpr int GRAM_ROW_BYTES = 128;
 constexpr int GRAM_STAGES = 2;
 constexpr int GRAM_GROUP_ROWS = 4;  // block-rows per L2 locality group
