@@ -41,8 +41,10 @@ __device__ __forceinline__ double readlane_d(double v, int l) {
   int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
   return __hiloint2double(hi, lo);
 }
+// (ad, ai) < (bd, bi) lexicographically; bitwise, so it compiles to three
+// compares and two mask operations instead of short-circuit branches.
 __device__ __forceinline__ bool key_less(double ad, int ai, double bd, int bi) {
-  return ad < bd || (ad == bd && ai < bi);
+  return (ad < bd) | ((ad == bd) & (ai < bi));
 }
 
 template <int LMAX, bool SWEEP, int R>
@@ -160,7 +162,7 @@ __global__ __launch_bounds__(64) void window_topk_kernel(
         const bool valid = adelta >= L && col >= 0 && col < npL;
         const double td = readlane_d(thr_d[0], s);
         const int ti = __builtin_amdgcn_readlane(thr_i[0], s);
-        const uint64_t mask = __ballot(valid && key_less(D, col, td, ti));
+        const uint64_t mask = __ballot(valid & key_less(D, col, td, ti));
         if (mask)
           insert_candidates(mask, D, col, s, k, ld, li_, s * k, lane, thr_d[0], thr_i[0]);
         if (s + 1 < R)
@@ -180,7 +182,7 @@ __global__ __launch_bounds__(64) void window_topk_kernel(
             const bool valid = adelta >= L && col >= 0 && col < npL;
             const double td = readlane_d(thr_d[L - 1], s);
             const int ti = __builtin_amdgcn_readlane(thr_i[L - 1], s);
-            const uint64_t mask = __ballot(valid && key_less(D, col, td, ti));
+            const uint64_t mask = __ballot(valid & key_less(D, col, td, ti));
             if (mask)
               insert_candidates(mask, D, col, s, k, ld, li_, ((L - 1) * R + s) * k,
                                 lane, thr_d[L - 1], thr_i[L - 1]);
@@ -202,6 +204,223 @@ __global__ __launch_bounds__(64) void window_topk_kernel(
       part_i[o] = li_[q];
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// Single trajectory length, register-resident (the headline path).
+//
+// Each lane keeps the R + L - 1 values of its diagonal for the current chunk
+// in registers (the next chunk's values are loaded meanwhile) and the R-step
+// recurrence is fully unrolled, so a step is: two FP64 adds, three readlanes
+// of the row's threshold, a few compares folded into one ballot, and a branch
+// that is almost never taken.
+//
+// The first chunk of a wave seeds each row's list with a wave-wide bitonic
+// sort of its 64 candidates (the lists start empty, so every candidate would
+// otherwise be inserted one by one). Later insertions shift the list one lane
+// with DPP wave_shr:1, a VALU move, instead of an LDS permute.
+// ---------------------------------------------------------------------------
+constexpr int W1_ROWS = 32;   // rows per wave
+constexpr int W1_GROUP = 8;   // steps unrolled per group
+#define W1_VALS_BYTES(M) (((size_t)(M) * 64 * sizeof(float) + 15) / 16 * 16)
+
+__device__ __forceinline__ double dpp_shr1_d(double v, double old) {
+  const int lo = __builtin_amdgcn_update_dpp(__double2loint(old), __double2loint(v), 0x138, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(__double2hiint(old), __double2hiint(v), 0x138, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ int dpp_shr1_i(int v, int old) {
+  return __builtin_amdgcn_update_dpp(old, v, 0x138, 0xF, 0xF, false);
+}
+
+// Insert the ballot's candidates (D, col) of row s into its sorted list
+// (lane q < k holds entry q while inserting) and refresh the row threshold
+// kept by lane s.
+__device__ __forceinline__ void insert_seq(uint64_t mask, double D, int col, int k,
+                                           double* rd, int* ri, int lane, int s,
+                                           double& thr_d, int& thr_i) {
+  double ed = lane < k ? rd[lane] : __builtin_huge_val();
+  int ei = lane < k ? ri[lane] : INT_MAX;
+  while (mask) {
+    const int src = __builtin_ctzll(mask);
+    mask &= mask - 1;
+    const double cd = readlane_d(D, src);
+    const int ci = __builtin_amdgcn_readlane(col, src);
+    const double kd = readlane_d(ed, k - 1);
+    const int ki = __builtin_amdgcn_readlane(ei, k - 1);
+    if (!key_less(cd, ci, kd, ki)) continue;
+    const double pd = dpp_shr1_d(ed, -__builtin_huge_val());  // lane 0: -inf
+    const int pi = dpp_shr1_i(ei, INT_MIN);
+    const bool lt_prev = key_less(cd, ci, pd, pi);
+    const bool lt_self = key_less(cd, ci, ed, ei);
+    ed = lt_prev ? pd : (lt_self ? cd : ed);
+    ei = lt_prev ? pi : (lt_self ? ci : ei);
+  }
+  if (lane < k) {
+    rd[lane] = ed;
+    ri[lane] = ei;
+  }
+  const double nd = readlane_d(ed, k - 1);
+  const int ni = __builtin_amdgcn_readlane(ei, k - 1);
+  if (lane == s) {
+    thr_d = nd;
+    thr_i = ni;
+  }
+}
+
+// Seed row s's list with the k smallest of this step's 64 candidates: bitonic
+// sort of (D, col) across the wave (invalid lanes carry +inf and a distinct
+// index above every column), lanes q < k keep the q-th smallest.
+__device__ __forceinline__ void seed_row(double d, int c, bool valid, int k, double* rd,
+                                         int* ri, int lane, int s, double& thr_d,
+                                         int& thr_i) {
+  if (!valid) {
+    d = __builtin_huge_val();
+    c = INT_MAX - 64 + lane;
+  }
+#pragma unroll 1
+  for (int size = 2; size <= 64; size <<= 1)
+#pragma unroll 1
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      const double pd = __shfl_xor(d, stride, 64);
+      const int pc = __shfl_xor(c, stride, 64);
+      const bool asc = (lane & size) == 0;
+      const bool lower = (lane & stride) == 0;
+      const bool p_less = key_less(pd, pc, d, c);
+      if ((lower == asc) == p_less) {
+        d = pd;
+        c = pc;
+      }
+    }
+  const bool sentinel = d == __builtin_huge_val();
+  if (lane < k) {
+    rd[lane] = d;
+    ri[lane] = sentinel ? INT_MAX : c;
+  }
+  const double nd = readlane_d(d, k - 1);
+  const int nc = __builtin_amdgcn_readlane(c, k - 1);
+  if (lane == s) {
+    thr_d = nd;
+    thr_i = nd == __builtin_huge_val() ? INT_MAX : nc;
+  }
+}
+
+template <int L>
+__global__ __launch_bounds__(64) void window1_kernel(
+    const float* __restrict__ S, int64_t ldS, int T, int k, int W, int64_t units,
+    double* __restrict__ part_d, int32_t* __restrict__ part_i) {
+  constexpr int R = W1_ROWS;
+  constexpr int U = W1_GROUP;
+  constexpr int M = R + L - 1;
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  float* vl = (float*)smem;                                    // [M][64]
+  double* ld = (double*)(smem + (size_t)W1_VALS_BYTES(M));     // [R][k]
+  int* li = (int*)(ld + (size_t)R * k);                        // [R][k]
+  const int lane = threadIdx.x;
+  const int64_t unit = blockIdx.x;
+  const int npL = T - L + 1;
+  const int rb = (int)(unit / W), split = (int)(unit % W);
+  const int r0 = rb * R;
+  const int64_t dlo = -(int64_t)(r0 + R - 1);
+  const int64_t NC = ((int64_t)npL + R - 1 + 63) / 64;
+  const int64_t cb = (int64_t)split * NC / W, ce = (int64_t)(split + 1) * NC / W;
+
+  double thr_d = __builtin_huge_val();
+  int thr_i = INT_MAX;
+
+  // Values of diagonal delta at rows r0 + m (one 256-byte segment per row
+  // for the wave), zero outside the matrix. The pointer walks down the rows
+  // with a stride the compiler treats as opaque, so no per-row address is
+  // precomputed and held across chunks; chunks wholly inside the matrix skip
+  // the bounds tests, the others read a safe element and discard it.
+  float nxt[M];
+  auto load = [&](int64_t c) __attribute__((always_inline)) {
+    const int64_t dc = dlo + 64 * c;
+    int64_t stride = ldS + 1;
+    asm volatile("" : "+s"(stride));
+    const float* p = S + ((int64_t)r0 * stride + dc + lane);
+    const bool inb = r0 + dc >= 0 && (int64_t)r0 + M - 1 < T && r0 + M - 1 + dc + 63 < T;
+    if (inb) {
+#pragma unroll
+      for (int m = 0; m < M; ++m) {
+        nxt[m] = *p;
+        p += stride;
+      }
+    } else {
+      const int64_t delta = dc + lane;
+      int rows_in = T - r0;  // rows r0 + m with m < rows_in exist
+      asm volatile("" : "+s"(rows_in));
+#pragma unroll
+      for (int m = 0; m < M; ++m) {
+        const int64_t col = r0 + m + delta;
+        const bool ok = (m < rows_in) & (col >= 0) & (col < T);
+        const float x = *(ok ? p : S);
+        nxt[m] = ok ? x : 0.f;
+        p += stride;
+      }
+    }
+  };
+
+  load(cb);
+  for (int64_t c = cb; c < ce; ++c) {
+    // park this chunk's values in LDS, then start fetching the next chunk
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < M; ++m) vl[m * 64 + lane] = nxt[m];
+    __syncthreads();
+    if (c + 1 < ce) load(c + 1);
+    const int delta = (int)(dlo + 64 * c) + lane;
+    const int adelta = delta < 0 ? -delta : delta;
+    const bool okd = adelta >= L;
+    const bool first = c == cb;
+    double D = 0.0;
+#pragma unroll
+    for (int l = 0; l < L; ++l) D += (double)vl[l * 64 + lane];
+#pragma unroll 1
+    for (int g = 0; g < R; g += U) {
+      float w[U + L];
+#pragma unroll
+      for (int j = 0; j < U + L && g + j < M; ++j) w[j] = vl[(g + j) * 64 + lane];
+#pragma unroll
+      for (int j = 0; j < U; ++j) {
+        const int s = g + j;
+        const int r = r0 + s;
+        if (r < npL) {
+          const int col = r + delta;
+          const bool valid = okd & ((unsigned)col < (unsigned)npL);
+          if (first) {
+            // the lists start empty: seed each with a sort of its 64 candidates
+            seed_row(D, col, valid, k, ld + s * k, li + s * k, lane, s, thr_d, thr_i);
+          } else {
+            const double td = readlane_d(thr_d, s);
+            const int ti = __builtin_amdgcn_readlane(thr_i, s);
+            const uint64_t mask = __ballot(valid & key_less(D, col, td, ti));
+            if (mask) insert_seq(mask, D, col, k, ld + s * k, li + s * k, lane, s, thr_d, thr_i);
+          }
+        }
+        if (s + 1 < R) D = (D - (double)w[j]) + (double)w[j + L];
+      }
+    }
+  }
+  // partial lists: part[(split * npL + row) * k + q]
+  for (int s = 0; s < R; ++s) {
+    const int row = r0 + s;
+    if (row >= npL) break;
+    if (lane < k) {
+      const int64_t o = ((int64_t)split * npL + row) * k + lane;
+      part_d[o] = ld[s * k + lane];
+      part_i[o] = li[s * k + lane];
+    }
+  }
+}
+
+template <int L>
+hipError_t launch_win1(const float* S, int64_t ldS, int T, int k, int W, int64_t units,
+                       double* pd, int32_t* pi, hipStream_t s) {
+  const size_t lds = W1_VALS_BYTES(W1_ROWS + L - 1) + (size_t)W1_ROWS * k * 12;
+  hipLaunchKernelGGL((window1_kernel<L>), dim3((unsigned)units), dim3(64), lds, s, S, ldS,
+                     T, k, W, units, pd, pi);
+  return hipGetLastError();
 }
 
 __global__ __launch_bounds__(256) void merge_kernel(
@@ -322,9 +541,32 @@ hipError_t launch_window_topk(const float* S, int64_t ldS, int64_t T, int L_min,
                               int64_t units, size_t lds_bytes, double* part_d,
                               int32_t* part_i, hipStream_t s) {
   const int np0 = (int)(T - L_min + 1);
-  if (L_min == L_max)
-    return launch_win_l<false>(L_max, rows, S, ldS, (int)T, np0, k, splits,
-                               units, lds_bytes, part_d, part_i, s);
+  if (L_min == L_max) {
+    switch (L_max) {
+#define TRAKNN_WIN1_CASE(n) \
+  case n:                   \
+    return launch_win1<n>(S, ldS, (int)T, k, splits, units, part_d, part_i, s);
+      TRAKNN_WIN1_CASE(1)
+      TRAKNN_WIN1_CASE(2)
+      TRAKNN_WIN1_CASE(3)
+      TRAKNN_WIN1_CASE(4)
+      TRAKNN_WIN1_CASE(5)
+      TRAKNN_WIN1_CASE(6)
+      TRAKNN_WIN1_CASE(7)
+      TRAKNN_WIN1_CASE(8)
+      TRAKNN_WIN1_CASE(9)
+      TRAKNN_WIN1_CASE(10)
+      TRAKNN_WIN1_CASE(11)
+      TRAKNN_WIN1_CASE(12)
+      TRAKNN_WIN1_CASE(13)
+      TRAKNN_WIN1_CASE(14)
+      TRAKNN_WIN1_CASE(15)
+      TRAKNN_WIN1_CASE(16)
+#undef TRAKNN_WIN1_CASE
+      default:
+        return hipErrorInvalidValue;
+    }
+  }
   if (L_min != 1) return hipErrorInvalidValue;
   return launch_win_l<true>(L_max, rows, S, ldS, (int)T, np0, k, splits, units,
                             lds_bytes, part_d, part_i, s);
