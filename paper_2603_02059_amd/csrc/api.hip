@@ -16,7 +16,10 @@ constexpr size_t WS_ALIGN = 256;
 constexpr int64_t MAX_T = 1 << 20;       // int32 indices with headroom
 constexpr int64_t MAX_D = (int64_t)1 << 28;
 constexpr size_t MAX_WIN_LDS = 64 * 1024;
-constexpr int64_t WIN_TARGET_UNITS = 4096;
+#ifndef TRAKNN_WIN_TARGET_UNITS
+#define TRAKNN_WIN_TARGET_UNITS 4096
+#endif
+constexpr int64_t WIN_TARGET_UNITS = TRAKNN_WIN_TARGET_UNITS;
 constexpr int MAX_SPLITS = 16;
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -29,8 +32,31 @@ int fail_hip(hipError_t e) { return e == hipSuccess ? TRAKNN_OK : TRAKNN_ERR_HIP
 // Choose rows per window wave and column splits. R = 32 keeps the diagonal
 // chunk's LDS staging and list storage small; R = 4 serves large k * NL (up to
 // 16 lengths x 64 neighbours).
+//
+// A single length runs one workgroup of W waves per block of WINDOW1_ROWS rows
+// (the waves split the row block's diagonals and share a per-row bound), with
+// W as large as the LDS budget and the target parallelism allow.
 bool plan_window(traknn_plan_s* p) {
   const int k = p->cfg.k;
+  if (p->NL == 1) {
+    const int L = p->cfg.L_max;
+    const int64_t nrb = (p->np0 + WINDOW1_ROWS - 1) / WINDOW1_ROWS;
+    const int64_t nchunks = (p->np0 + WINDOW1_ROWS - 1 + 63) / 64;
+    const size_t base = window1_lds_bytes(L, k, 0);
+    const size_t per_wave = window1_lds_bytes(L, k, 1) - base;
+    if (base + per_wave > MAX_WIN_LDS) return false;
+    int64_t W = (WIN_TARGET_UNITS + nrb - 1) / nrb;
+    const int64_t wmax = (int64_t)((MAX_WIN_LDS - base) / per_wave);
+    if (W > wmax) W = wmax;
+    if (W > MAX_SPLITS) W = MAX_SPLITS;
+    if (W > nchunks) W = nchunks;
+    if (W < 1) W = 1;
+    p->win_rows = WINDOW1_ROWS;
+    p->win_splits = (int)W;
+    p->win_units = nrb * W;
+    p->win_lds = window1_lds_bytes(L, k, (int)W);
+    return true;
+  }
   int rows = 32;
   size_t lds = window_lds_bytes(p->cfg.L_max, p->NL, k, rows);
   if (lds > MAX_WIN_LDS) {

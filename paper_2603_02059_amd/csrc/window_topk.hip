@@ -30,6 +30,7 @@
 // order. Everything is deterministic (no atomics).
 #include <cfloat>
 #include <climits>
+#include <type_traits>
 
 #include "internal.h"
 
@@ -220,7 +221,7 @@ __global__ __launch_bounds__(64) void window_topk_kernel(
 // otherwise be inserted one by one). Later insertions shift the list one lane
 // with DPP wave_shr:1, a VALU move, instead of an LDS permute.
 // ---------------------------------------------------------------------------
-constexpr int W1_ROWS = 32;   // rows per wave
+constexpr int W1_ROWS = WINDOW1_ROWS;  // rows per wave
 constexpr int W1_GROUP = 8;   // steps unrolled per group
 #define W1_VALS_BYTES(M) (((size_t)(M) * 64 * sizeof(float) + 15) / 16 * 16)
 
@@ -305,27 +306,50 @@ __device__ __forceinline__ void seed_row(double d, int c, bool valid, int k, dou
   }
 }
 
+// One workgroup per row block: wave w scans every W-th chunk of 64 diagonals,
+// starting at chunk w, and keeps its own partial lists. The waves also share
+// one distance bound per row in LDS -- the smallest k-th distance any of them
+// has reached -- and skip candidates above it: such a candidate already has k
+// better ones elsewhere, so it cannot be among the row's k nearest
+// (candidates equal to the bound still reach the exact (distance, index)
+// test). Without the shared bound every wave rediscovers a tight threshold
+// on its own and the insertions grow with W.
+//
+// The steps of a group of U rows only filter (one compare against the row's
+// bound per step, ballots kept in SGPRs); the rare insertions of the group run
+// afterwards, which is exact because every row of a group is a different row.
+// Chunks wholly inside the row range and clear of the exclusion zone (all but
+// a few per row block) skip the per-lane validity tests.
 template <int L>
-__global__ __launch_bounds__(64) void window1_kernel(
-    const float* __restrict__ S, int64_t ldS, int T, int k, int W, int64_t units,
+__global__ __launch_bounds__(1024) void window1_kernel(
+    const float* __restrict__ S, int64_t ldS, int T, int k, int W,
     double* __restrict__ part_d, int32_t* __restrict__ part_i) {
   constexpr int R = W1_ROWS;
   constexpr int U = W1_GROUP;
   constexpr int M = R + L - 1;
   extern __shared__ __attribute__((aligned(16))) char smem[];
-  float* vl = (float*)smem;                                    // [M][64]
-  double* ld = (double*)(smem + (size_t)W1_VALS_BYTES(M));     // [R][k]
-  int* li = (int*)(ld + (size_t)R * k);                        // [R][k]
-  const int lane = threadIdx.x;
-  const int64_t unit = blockIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int split = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  unsigned long long* shb = (unsigned long long*)smem;  // [R] bits of the shared bound
+  char* mine = smem + R * sizeof(unsigned long long) +
+               (size_t)split * (W1_VALS_BYTES(M + U) + (size_t)R * k * 12);
+  float* vl = (float*)mine;  // [M + U][64]: M rows of values, U rows of padding
+  double* ld = (double*)(mine + W1_VALS_BYTES(M + U));  // [R][k]
+  int* li = (int*)(ld + (size_t)R * k);                   // [R][k]
+  if (threadIdx.x < R) shb[threadIdx.x] = (unsigned long long)__double_as_longlong(__builtin_huge_val());
+  __syncthreads();  // the only workgroup barrier: the waves' trip counts differ
+
   const int npL = T - L + 1;
-  const int rb = (int)(unit / W), split = (int)(unit % W);
-  const int r0 = rb * R;
+  const int r0 = blockIdx.x * R;
+  const int nrows = npL - r0 < R ? npL - r0 : R;  // rows of this block
   const int64_t dlo = -(int64_t)(r0 + R - 1);
   const int64_t NC = ((int64_t)npL + R - 1 + 63) / 64;
-  const int64_t cb = (int64_t)split * NC / W, ce = (int64_t)(split + 1) * NC / W;
+  // wave `split` takes chunks split, split + W, ...: the W waves of the block
+  // move along the rows side by side, so together they read W * 256
+  // contiguous bytes of each row at a time
+  const int64_t cb = split, ce = NC;
 
-  double thr_d = __builtin_huge_val();
+  double thr_d = __builtin_huge_val();  // lane q: own k-th of row r0 + q
   int thr_i = INT_MAX;
 
   // Values of diagonal delta at rows r0 + m (one 256-byte segment per row
@@ -347,69 +371,120 @@ __global__ __launch_bounds__(64) void window1_kernel(
         p += stride;
       }
     } else {
-      const int64_t delta = dc + lane;
       int rows_in = T - r0;  // rows r0 + m with m < rows_in exist
-      asm volatile("" : "+s"(rows_in));
+      int64_t Tl = T;
+      asm volatile("" : "+s"(rows_in), "+s"(Tl));
+      int64_t col = r0 + dc + lane;  // column of row r0 + m, stepped with m
 #pragma unroll
       for (int m = 0; m < M; ++m) {
-        const int64_t col = r0 + m + delta;
-        const bool ok = (m < rows_in) & (col >= 0) & (col < T);
+        const bool ok = (m < rows_in) & (col >= 0) & (col < Tl);
         const float x = *(ok ? p : S);
         nxt[m] = ok ? x : 0.f;
         p += stride;
+        col += 1;
       }
     }
   };
+  // after the row's own list changed: lower the shared bound to its k-th
+  auto publish = [&](int s) __attribute__((always_inline)) {
+    if (lane == s && thr_d != __builtin_huge_val())
+      atomicMin(&shb[s], (unsigned long long)__double_as_longlong(thr_d));
+  };
 
-  load(cb);
-  for (int64_t c = cb; c < ce; ++c) {
-    // park this chunk's values in LDS, then start fetching the next chunk
-    __syncthreads();
-#pragma unroll
-    for (int m = 0; m < M; ++m) vl[m * 64 + lane] = nxt[m];
-    __syncthreads();
-    if (c + 1 < ce) load(c + 1);
+  // First chunk of the range: the lists start empty, so each row's list is
+  // seeded with a sort of its first 64 candidates.
+  auto seed_chunk = [&](int64_t c) __attribute__((always_inline)) {
     const int delta = (int)(dlo + 64 * c) + lane;
-    const int adelta = delta < 0 ? -delta : delta;
-    const bool okd = adelta >= L;
-    const bool first = c == cb;
+    const bool okd = (delta >= L) | (delta <= -L);
+    double D = 0.0;
+#pragma unroll
+    for (int l = 0; l < L; ++l) D += (double)vl[l * 64 + lane];
+#pragma unroll 1
+    for (int s = 0; s < nrows; ++s) {
+      const int col = r0 + s + delta;
+      const bool valid = okd & ((unsigned)col < (unsigned)npL);
+      seed_row(D, col, valid, k, ld + s * k, li + s * k, lane, s, thr_d, thr_i);
+      publish(s);
+      D = (D - (double)vl[s * 64 + lane]) + (double)vl[(s + L) * 64 + lane];
+    }
+  };
+
+  // Later chunks: filter, then insert. EDGE chunks test each candidate's
+  // column range, exclusion zone and row.
+  auto scan_chunk = [&](int64_t c, auto edge_c) __attribute__((always_inline)) {
+    constexpr bool EDGE = decltype(edge_c)::value;
+    const int delta = (int)(dlo + 64 * c) + lane;
+    const bool okd = (delta >= L) | (delta <= -L);
     double D = 0.0;
 #pragma unroll
     for (int l = 0; l < L; ++l) D += (double)vl[l * 64 + lane];
 #pragma unroll 1
     for (int g = 0; g < R; g += U) {
-      float w[U + L];
+      float w[U + L];  // rows g .. g+U+L-1
 #pragma unroll
-      for (int j = 0; j < U + L && g + j < M; ++j) w[j] = vl[(g + j) * 64 + lane];
+      for (int j = 0; j < U + L; ++j) w[j] = vl[(g + j) * 64 + lane];
+      // bound per row (lane q < R): own k-th or the shared bound, the smaller
+      const double sh = __longlong_as_double(
+          (long long)__atomic_load_n(&shb[lane & (R - 1)], __ATOMIC_RELAXED));
+      const double bound = __builtin_fmin(thr_d, sh);
+      double Dj[U];
+      uint64_t m[U];
+      uint64_t any = 0;
 #pragma unroll
       for (int j = 0; j < U; ++j) {
         const int s = g + j;
-        const int r = r0 + s;
-        if (r < npL) {
-          const int col = r + delta;
-          const bool valid = okd & ((unsigned)col < (unsigned)npL);
-          if (first) {
-            // the lists start empty: seed each with a sort of its 64 candidates
-            seed_row(D, col, valid, k, ld + s * k, li + s * k, lane, s, thr_d, thr_i);
-          } else {
-            const double td = readlane_d(thr_d, s);
-            const int ti = __builtin_amdgcn_readlane(thr_i, s);
-            const uint64_t mask = __ballot(valid & key_less(D, col, td, ti));
-            if (mask) insert_seq(mask, D, col, k, ld + s * k, li + s * k, lane, s, thr_d, thr_i);
+        Dj[j] = D;
+        bool pass = D <= readlane_d(bound, s);
+        if constexpr (EDGE) {
+          const int col = r0 + s + delta;
+          pass = pass & okd & ((unsigned)col < (unsigned)npL) & (s < nrows);
+        }
+        m[j] = __ballot(pass);
+        any |= m[j];
+        if (j + 1 < U || g + U < R) D = (D - (double)w[j]) + (double)w[j + L];
+      }
+      if (any) {
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+          if (m[j]) {
+            const int s = g + j;
+            insert_seq(m[j], Dj[j], r0 + s + delta, k, ld + s * k, li + s * k, lane, s,
+                       thr_d, thr_i);
+            publish(s);
           }
         }
-        if (s + 1 < R) D = (D - (double)w[j]) + (double)w[j + L];
       }
     }
+  };
+
+  if (cb < ce) load(cb);
+  const bool full = nrows == R;
+  for (int64_t c = cb; c < ce; c += W) {
+    // park this chunk's values in this wave's LDS rows (LDS accesses of a
+    // wave execute in order), then start fetching the next chunk
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int m = 0; m < M; ++m) vl[m * 64 + lane] = nxt[m];
+    __builtin_amdgcn_wave_barrier();
+    if (c + W < ce) load(c + W);
+    const int64_t dc = dlo + 64 * c;
+    const bool interior = full & ((dc >= L) | (dc + 63 <= -L)) & (r0 + dc >= 0) &
+                          (r0 + R - 1 + dc + 63 < npL);
+    if (c == cb)
+      seed_chunk(c);
+    else if (interior)
+      scan_chunk(c, std::false_type{});
+    else
+      scan_chunk(c, std::true_type{});
   }
-  // partial lists: part[(split * npL + row) * k + q]
-  for (int s = 0; s < R; ++s) {
+  // partial lists: part[(split * npL + row) * k + q]; a range with no chunk
+  // leaves its lists empty
+  for (int s = 0; s < nrows; ++s) {
     const int row = r0 + s;
-    if (row >= npL) break;
     if (lane < k) {
       const int64_t o = ((int64_t)split * npL + row) * k + lane;
-      part_d[o] = ld[s * k + lane];
-      part_i[o] = li[s * k + lane];
+      part_d[o] = cb < ce ? ld[s * k + lane] : __builtin_huge_val();
+      part_i[o] = cb < ce ? li[s * k + lane] : INT_MAX;
     }
   }
 }
@@ -417,9 +492,10 @@ __global__ __launch_bounds__(64) void window1_kernel(
 template <int L>
 hipError_t launch_win1(const float* S, int64_t ldS, int T, int k, int W, int64_t units,
                        double* pd, int32_t* pi, hipStream_t s) {
-  const size_t lds = W1_VALS_BYTES(W1_ROWS + L - 1) + (size_t)W1_ROWS * k * 12;
-  hipLaunchKernelGGL((window1_kernel<L>), dim3((unsigned)units), dim3(64), lds, s, S, ldS,
-                     T, k, W, units, pd, pi);
+  const size_t lds = window1_lds_bytes(L, k, W);
+  const unsigned blocks = (unsigned)(units / W);
+  hipLaunchKernelGGL((window1_kernel<L>), dim3(blocks), dim3(64 * W), lds, s, S, ldS,
+                     T, k, W, pd, pi);
   return hipGetLastError();
 }
 
@@ -531,6 +607,11 @@ hipError_t launch_win_l(int L, int rows, const float* S, int64_t ldS, int T,
 }
 
 }  // namespace
+
+size_t window1_lds_bytes(int L, int k, int W) {
+  return (size_t)W1_ROWS * sizeof(unsigned long long) +
+         (size_t)W * (W1_VALS_BYTES(W1_ROWS + L - 1 + W1_GROUP) + (size_t)W1_ROWS * k * 12);
+}
 
 size_t window_lds_bytes(int L_max, int NL, int k, int rows) {
   return (size_t)(rows + L_max - 1) * 64 * sizeof(float) + (size_t)NL * rows * k * 12;
