@@ -88,7 +88,7 @@ void plan_layout(traknn_plan_s* p) {
   const int prec = p->cfg.precision;
   L.mu_part = take((size_t)p->tchunks * p->D * sizeof(double));
   L.mu = take((size_t)p->D * sizeof(double));
-  L.norm = take((size_t)p->Tpad * sizeof(double));
+  L.ncs = take((size_t)norm_chunks(p->Dpad) * p->Tpad * sizeof(float));
   L.xc = take((size_t)p->Tpad * p->Dpad * elem_bytes(prec));
   L.S = take((size_t)p->T * p->ldS * sizeof(float));
   const size_t nparts = (size_t)p->win_splits * p->NL * p->np0 * p->cfg.k;
@@ -240,7 +240,7 @@ int traknn_knn(traknn_plan_t plan, const float* X, int64_t ldx, void* workspace,
   const Layout& L = plan->lay;
   double* mu_part = at<double>(workspace, L.mu_part);
   double* mu = at<double>(workspace, L.mu);
-  double* norm = at<double>(workspace, L.norm);
+  float* ncs = at<float>(workspace, L.ncs);
   void* xc = at<char>(workspace, L.xc);
   float* S = at<float>(workspace, L.S);
   double* part_d = at<double>(workspace, L.part_d);
@@ -253,10 +253,10 @@ int traknn_knn(traknn_plan_t plan, const float* X, int64_t ldx, void* workspace,
   if ((rc = record(plan, 1, s))) return rc;
   if ((rc = fail_hip(launch_centre_convert(X, ldx, plan->T, plan->D, plan->Tpad,
                                            plan->Dpad, c.precision, mu, xc,
-                                           norm, s))))
+                                           ncs, s))))
     return rc;
   if ((rc = record(plan, 2, s))) return rc;
-  if ((rc = fail_hip(launch_gram(xc, norm, plan->T, plan->Dpad, plan->nb,
+  if ((rc = fail_hip(launch_gram(xc, ncs, plan->T, plan->Tpad, plan->Dpad, plan->nb,
                                  plan->ntiles, c.precision, S, plan->ldS, s))))
     return rc;
   if ((rc = record(plan, 3, s))) return rc;

@@ -1,12 +1,21 @@
 // Symmetric Gram product and distance epilogue (paper, Algorithm 1 stage 1 and
 // Eq. 4): for every tile pair I <= J of 256 fields,
-//   G_IJ = Xc_I Xc_J^T          (MFMA, FP32 accumulation)
-//   d(i,j) = N_i + N_j - 2 G_ij (FP64), stored FP32 at (i,j) and (j,i).
-// Only the upper triangle of tile pairs is computed, which halves the
-// contraction as the paper's symmetric batching does.
+//   d(i,j) = N_i + N_j - 2 <x_i, x_j>   (MFMA, FP32 accumulation),
+// stored FP32 at (i,j) and (j,i). Only the upper triangle of tile pairs is
+// computed, which halves the contraction as the paper's symmetric batching
+// does.
 //
-// Tiling for gfx950: 256 threads = 4 wave64s in a 2x2 arrangement, each wave
-// owning a 128x128 block = 4x4 MFMA 32x32 blocks held in accumulation
+// Distance-form accumulation: K runs in chunks of GRAM_CHUNK elements, and once
+// a chunk's products are in the accumulators, one extra FP32 MFMA of depth 2
+// adds -(N_i^c + N_j^c)/2, the chunk's squared norms (FP64 sums rounded to
+// FP32, from the centring pass). The accumulators then hold -d/2 over the
+// finished chunks, so they never grow much beyond the distance itself: their
+// FP32 rounding errors scale with d + N/(number of chunks) instead of with the
+// norms N, which for near neighbours are several times larger than d. The
+// epilogue only scales by -2.
+//
+// Tiling for gfx950: 512 threads = 8 wave64s in a 2x4 arrangement, each wave
+// owning a 128x64 block = 4x2 MFMA 32x32 blocks held in accumulation
 // registers. Every K stage brings 128 bytes of each of the 512 operand rows
 // into LDS (2 x 32 KB), double buffered. Rows are stored with their eight
 // 16-byte chunks XOR-swizzled by the row index so that the ds_read_b128
@@ -39,9 +48,10 @@ static_assert(WT_M == 128, "the epilogue parks 32-row bands of 128-row wave tile
 // s_waitcnt immediate waiting for vmcnt == 0 only (expcnt, lgkmcnt at max)
 constexpr int VMCNT0 = 0x0F70;
 constexpr int EPI_PITCH = 36;  // floats per parked accumulator column (32 + 4)
-static_assert((GRAM_THREADS / 64) * (TILE / (GRAM_THREADS / 64 / 2)) * EPI_PITCH * 4 +
-                  2 * TILE * 8 <= GRAM_STAGES * 2 * TILE * RB,
+static_assert((GRAM_THREADS / 64) * (TILE / (GRAM_THREADS / 64 / 2)) * EPI_PITCH * 4 <=
+                  GRAM_STAGES * 2 * TILE * RB,
               "epilogue staging must fit in the operand LDS");
+constexpr int NORM_LDS = 2 * 2 * TILE * 4;  // two chunks' norms of the I and J rows
 
 // Physical 16-byte slot of logical chunk `chunk` in LDS row `row`. The XOR key
 // (row ^ row>>3) & 7 makes any 8 aligned consecutive rows use 8 distinct
@@ -203,9 +213,10 @@ __device__ __forceinline__ void compute_stage(const char* __restrict__ A,
 template <int PREC>
 __global__ __launch_bounds__(GRAM_THREADS, 1) void gram_kernel(
     const char* __restrict__ xc, int64_t pitch, int nstages,
-    const double* __restrict__ norm, int64_t T, int nb, int64_t ntiles,
+    const float* __restrict__ ncs, int64_t T, int64_t Tpad, int nb, int64_t ntiles,
     float* __restrict__ S, int64_t ldS) {
-  __shared__ __attribute__((aligned(16))) char lds[GRAM_STAGES * 2 * OPER_BYTES];
+  __shared__ __attribute__((aligned(16))) char lds[GRAM_STAGES * 2 * OPER_BYTES + NORM_LDS];
+  float* const nrm = (float*)(lds + GRAM_STAGES * 2 * OPER_BYTES);  // [2][I 256 | J 256]
   int I, J;
   if (!decode_tile(blockIdx.x, nb, ntiles, I, J)) return;
 
@@ -241,20 +252,58 @@ __global__ __launch_bounds__(GRAM_THREADS, 1) void gram_kernel(
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.f;
 
+  // Chunk norms: wave 0 fetches the chunk's 256 N_i^c, wave 1 the 256 N_j^c
+  // (one 1 KB direct load each) into the chunk's LDS slot.
+  auto issue_norms = [&](int ch) {
+    const float* src = ncs + (int64_t)ch * Tpad + (int64_t)(w == 0 ? I : J) * TILE + 4 * lane;
+    __builtin_amdgcn_global_load_lds(src, nrm + (ch & 1) * 2 * TILE + w * TILE, 16, 0, 0);
+  };
+  // acc += -(N_i^c + N_j^c)/2 as a depth-2 FP32 MFMA: lanes 0-31 supply
+  // k = 0 (A: N_i^c, B: -1/2), lanes 32-63 k = 1 (A: 1, B: -N_j^c/2); all
+  // products are exact.
+  const int r32 = lane & 31;
+  const bool khi = lane >= 32;
+  auto correct = [&](int ch) {
+    const float* nA = nrm + (ch & 1) * 2 * TILE;
+    const float* nB = nA + TILE;
+    float av[BM], bv[BN];
+#pragma unroll
+    for (int bm = 0; bm < BM; ++bm) {
+      const float x = nA[wm * WT_M + bm * 32 + r32];
+      av[bm] = khi ? 1.0f : x;
+    }
+#pragma unroll
+    for (int bn = 0; bn < BN; ++bn) {
+      const float y = nB[wn * WT_N + bn * 32 + r32];
+      bv[bn] = khi ? -0.5f * y : -0.5f;
+    }
+#pragma unroll
+    for (int bm = 0; bm < BM; ++bm)
+#pragma unroll
+      for (int bn = 0; bn < BN; ++bn)
+        acc[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[bm], bv[bn], acc[bm][bn], 0, 0, 0);
+  };
+  constexpr int SPC = GRAM_CHUNK / (PREC == TRAKNN_FP16 ? 64 : 32);  // stages per chunk
+
   issue(0, 0);
   __builtin_amdgcn_s_waitcnt(VMCNT0);
   __syncthreads();
   for (int st = 0; st < nstages; ++st) {
     const int buf = st & 1;
     const bool more = st + 1 < nstages;
+    const int ch = st / SPC;
+    const bool chunk_end = !more || (st + 1) % SPC == 0;
     if (more) issue(st + 1, buf ^ 1);
+    if (chunk_end && w < 2) issue_norms(ch);
     const char* A = lds + buf * 2 * OPER_BYTES;
     compute_stage<PREC>(A, A + OPER_BYTES, wm, wn, lane, acc);
-    if (more) __builtin_amdgcn_s_waitcnt(VMCNT0);
+    __builtin_amdgcn_s_waitcnt(VMCNT0);
     __syncthreads();
+    if (chunk_end) correct(ch);
   }
 
-  // Epilogue through LDS (the operand buffers are free now). Accumulator r of
+  // Epilogue through LDS (the operand buffers are free now): d = -2 acc.
+  // Accumulator r of
   // lane l in a 32x32 block holds row 8*(r/4) + 4*(l/32) + r%4, column l%32;
   // each 32-row band (bm) of every wave is parked column-major in LDS with
   // compile-time accumulator indices, then all threads write the band's
@@ -262,13 +311,6 @@ __global__ __launch_bounds__(GRAM_THREADS, 1) void gram_kernel(
   // the mirrored (j, i).
   constexpr int NWAVES = GRAM_THREADS / 64;
   float* stg = (float*)lds;  // [NWAVES][WT_N][EPI_PITCH]
-  double* nI = (double*)(lds + NWAVES * WT_N * EPI_PITCH * 4);  // [256]
-  double* nJ = nI + TILE;                                        // [256]
-  if (tid < TILE) {
-    const int64_t gi = (int64_t)I * TILE + tid, gj = (int64_t)J * TILE + tid;
-    nI[tid] = gi < T ? norm[gi] : 0.0;
-    nJ[tid] = gj < T ? norm[gj] : 0.0;
-  }
   const bool diag = I == J;
   const int64_t i_base = (int64_t)I * TILE, j_base = (int64_t)J * TILE;
 #pragma unroll
@@ -291,7 +333,6 @@ __global__ __launch_bounds__(GRAM_THREADS, 1) void gram_kernel(
       const int jl = tid & (TILE - 1);
       const int wn_ = jl / WT_N, c = jl % WT_N;
       const int64_t j = j_base + jl;
-      const double nj = nJ[jl];
       if (j < T) {
         for (int wm_ = tid / TILE; wm_ < WAVES_M; wm_ += GRAM_THREADS / TILE) {
           const float* src = stg + (wm_ * WAVES_N + wn_) * WT_N * EPI_PITCH + c * EPI_PITCH;
@@ -300,8 +341,8 @@ __global__ __launch_bounds__(GRAM_THREADS, 1) void gram_kernel(
             const int64_t i = i_base + il;
             if (i >= T) break;
             if (diag && il >= jl) continue;  // diagonal tile: strict upper half
-            const double v = nI[il] + nj - 2.0 * (double)src[r];
-            S[i * ldS + j] = v > 0.0 ? (float)v : 0.f;
+            const float v = -2.f * src[r];
+            S[i * ldS + j] = v > 0.f ? v : 0.f;
           }
         }
       }
@@ -317,12 +358,11 @@ __global__ __launch_bounds__(GRAM_THREADS, 1) void gram_kernel(
       const int64_t i0 = i_base + il0;
       const f32x4 g = *(const f32x4*)(stg + (wm_ * WAVES_N + wn_) * WT_N * EPI_PITCH +
                                        c * EPI_PITCH + 4 * q);
-      const double nj = nJ[jl];
       float f[4];
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const double v = nI[il0 + e] + nj - 2.0 * (double)g[e];
-        f[e] = v > 0.0 ? (float)v : 0.f;
+        const float v = -2.f * g[e];
+        f[e] = v > 0.f ? v : 0.f;
       }
       float* dst = S + j * ldS + i0;
       if (!diag && i0 + 3 < T) {
@@ -343,7 +383,7 @@ __global__ __launch_bounds__(GRAM_THREADS, 1) void gram_kernel(
 
 }  // namespace
 
-hipError_t launch_gram(const void* xc, const double* norm, int64_t T,
+hipError_t launch_gram(const void* xc, const float* ncs, int64_t T, int64_t Tpad,
                        int64_t Dpad, int nb, int64_t ntiles, int precision,
                        float* S, int64_t ldS, hipStream_t s) {
   const int64_t pitch = Dpad * elem_bytes(precision);
@@ -354,15 +394,15 @@ hipError_t launch_gram(const void* xc, const double* norm, int64_t T,
   switch (precision) {
     case TRAKNN_FP32:
       hipLaunchKernelGGL(gram_kernel<TRAKNN_FP32>, grid, dim3(GRAM_THREADS), 0,
-                         s, x, pitch, nstages, norm, T, nb, ntiles, S, ldS);
+                         s, x, pitch, nstages, ncs, T, Tpad, nb, ntiles, S, ldS);
       break;
     case TRAKNN_BF16X3:
       hipLaunchKernelGGL(gram_kernel<TRAKNN_BF16X3>, grid, dim3(GRAM_THREADS),
-                         0, s, x, pitch, nstages, norm, T, nb, ntiles, S, ldS);
+                         0, s, x, pitch, nstages, ncs, T, Tpad, nb, ntiles, S, ldS);
       break;
     default:
       hipLaunchKernelGGL(gram_kernel<TRAKNN_FP16>, grid, dim3(GRAM_THREADS), 0,
-                         s, x, pitch, nstages, norm, T, nb, ntiles, S, ldS);
+                         s, x, pitch, nstages, ncs, T, Tpad, nb, ntiles, S, ldS);
       break;
   }
   return hipGetLastError();

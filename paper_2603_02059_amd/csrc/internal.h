@@ -27,6 +27,14 @@ constexpr int NUM_XCD = 8;
 inline int stage_k(int precision) { return precision == TRAKNN_FP16 ? 64 : 32; }
 inline int elem_bytes(int precision) { return precision == TRAKNN_FP16 ? 2 : 4; }
 
+// K elements per norm chunk: the Gram accumulators subtract the two rows'
+// squared norms over each chunk once it is done (distance-form accumulation),
+// so the FP32 accumulators hold -d/2 of the finished chunks instead of the
+// inner product, and their rounding errors scale with the distance, not with
+// the norms. A multiple of every stage depth.
+constexpr int GRAM_CHUNK = 512;
+__host__ __device__ inline int64_t norm_chunks(int64_t Dpad) { return (Dpad + GRAM_CHUNK - 1) / GRAM_CHUNK; }
+
 // ---------------------------------------------------------------------------
 // Window / top-k stage.
 // ---------------------------------------------------------------------------
@@ -37,7 +45,7 @@ constexpr int NUM_STAGES = 5;
 constexpr int COLSTAT_ROWS = 64;  // rows per partial column-sum block
 
 struct Layout {
-  size_t mu_part, mu, norm, xc, S, part_d, part_i;  // forward
+  size_t mu_part, mu, ncs, xc, S, part_d, part_i;  // forward
   size_t bw_cnt, bw_ptr, bw_fill, bw_rev;            // backward
   size_t total;
 };
@@ -76,9 +84,9 @@ hipError_t launch_colstats(const float* X, int64_t ldx, int64_t T, int64_t D,
 hipError_t launch_centre_convert(const float* X, int64_t ldx, int64_t T,
                                  int64_t D, int64_t Tpad, int64_t Dpad,
                                  int precision, const double* mu, void* xc,
-                                 double* norm, hipStream_t s);
+                                 float* ncs, hipStream_t s);
 // gram.hip
-hipError_t launch_gram(const void* xc, const double* norm, int64_t T,
+hipError_t launch_gram(const void* xc, const float* ncs, int64_t T, int64_t Tpad,
                        int64_t Dpad, int nb, int64_t ntiles, int precision,
                        float* S, int64_t ldS, hipStream_t s);
 // window_topk.hip

@@ -4,11 +4,12 @@
 // Distances are translation invariant, so the fields are centred per grid cell
 // before the Gram product: with ~1e5 Pa offsets the uncentred inner products
 // would cancel against the norms and lose every bit the reduced-precision
-// paths carry. Means and centred values are FP64; the squared norm of each row
-// is the FP64 norm of exactly the vector the Gram stage represents (FP32, FP16
-// or hi + lo), so the epilogue N_i + N_j - 2G is a distance between the same
-// two vectors up to the accumulation error (and, for BF16x3, the zero-mean
-// lo.lo cross term).
+// paths carry. Means and centred values are FP64. The squared norms are taken
+// per chunk of GRAM_CHUNK elements, in FP64, of exactly the vector the Gram
+// stage represents (FP32, FP16 or hi + lo), so that the Gram stage's
+// N_i + N_j - 2G, assembled chunk by chunk, is a distance between the same two
+// vectors up to the accumulation error (and, for BF16x3, the zero-mean lo.lo
+// cross term).
 #include <hip/hip_bf16.h>
 #include <hip/hip_fp16.h>
 
@@ -42,14 +43,9 @@ __global__ __launch_bounds__(256) void colsum_reduce_kernel(
   mu[c] = s / (double)T;
 }
 
-__device__ inline double block_sum_256(double v, double* red) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  if (lane == 0) red[w] = v;
-  __syncthreads();
-  double t = 0.0;
-  if (threadIdx.x == 0) t = ((red[0] + red[1]) + red[2]) + red[3];
-  return t;
+__device__ inline double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
 }
 
 __device__ inline uint16_t bf16_bits_rne(float f) {
@@ -62,57 +58,58 @@ __device__ inline double bf16_bits_to_double(uint16_t b) {
   return (double)__uint_as_float((uint32_t)b << 16);
 }
 
-// One workgroup per (padded) row. PREC selects the emitted representation.
+// One workgroup of 4 waves per (padded) row; wave w converts the norm chunks
+// w, w + 4, ... of GRAM_CHUNK elements and writes each chunk's squared norm
+// (FP64 sum in a fixed order, stored FP32) to ncs[chunk * Tpad + row]. PREC
+// selects the emitted representation.
 template <int PREC>
 __global__ __launch_bounds__(256) void centre_convert_kernel(
     const float* __restrict__ X, int64_t ldx, int64_t T, int64_t D,
-    int64_t Dpad, const double* __restrict__ mu, void* __restrict__ xc,
-    double* __restrict__ norm) {
-  __shared__ double red[4];
+    int64_t Tpad, int64_t Dpad, const double* __restrict__ mu,
+    void* __restrict__ xc, float* __restrict__ ncs) {
   const int64_t i = blockIdx.x;
   const bool live = i < T;
-  double acc = 0.0;
-  if constexpr (PREC == TRAKNN_FP32) {
-    float* out = (float*)xc + i * Dpad;
-    for (int64_t c = threadIdx.x; c < Dpad; c += 256) {
-      double v = (live && c < D) ? (double)X[i * ldx + c] - mu[c] : 0.0;
-      float f = (float)v;
-      double fd = (double)f;
-      acc += fd * fd;
-      out[c] = f;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t nch = norm_chunks(Dpad);
+  for (int64_t ch = w; ch < nch; ch += 4) {
+    double acc = 0.0;
+#pragma unroll
+    for (int m = 0; m < GRAM_CHUNK / 64; ++m) {
+      const int64_t c = ch * GRAM_CHUNK + m * 64 + lane;
+      if (c >= Dpad) break;
+      const double v = (live && c < D) ? (double)X[i * ldx + c] - mu[c] : 0.0;
+      if constexpr (PREC == TRAKNN_FP32) {
+        const float f = (float)v;
+        const double fd = (double)f;
+        acc += fd * fd;
+        ((float*)xc)[i * Dpad + c] = f;
+      } else if constexpr (PREC == TRAKNN_FP16) {
+        const _Float16 h = (_Float16)(float)v;
+        const double hd = (double)(float)h;
+        acc += hd * hd;
+        ((_Float16*)xc)[i * Dpad + c] = h;
+      } else {
+        // BF16X3: 16-byte chunks alternate 8 hi values and the 8 matching lo
+        // values, so one 128-byte Gram stage row holds 32 (hi, lo) pairs.
+        const uint16_t hb = bf16_bits_rne((float)v);
+        const double hd = bf16_bits_to_double(hb);
+        const uint16_t lb = bf16_bits_rne((float)(v - hd));
+        const double ld = bf16_bits_to_double(lb);
+        // norm of the represented value hi + lo (exact in FP64). The Gram
+        // stage drops only the cross term lo_i.lo_j, which has zero mean; a
+        // norm made of the three kept products alone would bias every
+        // distance low by sum (lo_i - lo_j)^2 ~ 2.5e-6 (N_i + N_j).
+        const double xv = hd + ld;
+        acc += xv * xv;
+        uint16_t* out = (uint16_t*)xc + i * Dpad * 2;
+        const int64_t chunk = c >> 3, within = c & 7;
+        out[chunk * 16 + within] = hb;
+        out[chunk * 16 + 8 + within] = lb;
+      }
     }
-  } else if constexpr (PREC == TRAKNN_FP16) {
-    _Float16* out = (_Float16*)xc + i * Dpad;
-    for (int64_t c = threadIdx.x; c < Dpad; c += 256) {
-      double v = (live && c < D) ? (double)X[i * ldx + c] - mu[c] : 0.0;
-      _Float16 h = (_Float16)(float)v;
-      double hd = (double)(float)h;
-      acc += hd * hd;
-      out[c] = h;
-    }
-  } else {
-    // BF16X3: 16-byte chunks alternate 8 hi values and the 8 matching lo
-    // values, so one 128-byte Gram stage row holds 32 (hi, lo) pairs.
-    uint16_t* out = (uint16_t*)xc + i * Dpad * 2;
-    for (int64_t c = threadIdx.x; c < Dpad; c += 256) {
-      double v = (live && c < D) ? (double)X[i * ldx + c] - mu[c] : 0.0;
-      uint16_t hb = bf16_bits_rne((float)v);
-      double hd = bf16_bits_to_double(hb);
-      uint16_t lb = bf16_bits_rne((float)(v - hd));
-      double ld = bf16_bits_to_double(lb);
-      // norm of the represented value hi + lo (exact in FP64). The Gram stage
-      // drops only the cross term lo_i.lo_j, which has zero mean; a norm made of
-      // the three kept products alone would bias every distance low by
-      // sum (lo_i - lo_j)^2 ~ 2.5e-6 (N_i + N_j).
-      const double xv = hd + ld;
-      acc += xv * xv;
-      const int64_t chunk = c >> 3, within = c & 7;
-      out[chunk * 16 + within] = hb;
-      out[chunk * 16 + 8 + within] = lb;
-    }
+    acc = wave_sum(acc);
+    if (lane == 0) ncs[ch * Tpad + i] = live ? (float)acc : 0.f;
   }
-  double n = block_sum_256(acc, red);
-  if (threadIdx.x == 0) norm[i] = live ? n : 0.0;
 }
 
 }  // namespace
@@ -133,20 +130,20 @@ hipError_t launch_colstats(const float* X, int64_t ldx, int64_t T, int64_t D,
 hipError_t launch_centre_convert(const float* X, int64_t ldx, int64_t T,
                                  int64_t D, int64_t Tpad, int64_t Dpad,
                                  int precision, const double* mu, void* xc,
-                                 double* norm, hipStream_t s) {
+                                 float* ncs, hipStream_t s) {
   dim3 g((unsigned)Tpad);
   switch (precision) {
     case TRAKNN_FP32:
       hipLaunchKernelGGL(centre_convert_kernel<TRAKNN_FP32>, g, dim3(256), 0, s,
-                         X, ldx, T, D, Dpad, mu, xc, norm);
+                         X, ldx, T, D, Tpad, Dpad, mu, xc, ncs);
       break;
     case TRAKNN_BF16X3:
       hipLaunchKernelGGL(centre_convert_kernel<TRAKNN_BF16X3>, g, dim3(256), 0,
-                         s, X, ldx, T, D, Dpad, mu, xc, norm);
+                         s, X, ldx, T, D, Tpad, Dpad, mu, xc, ncs);
       break;
     default:
       hipLaunchKernelGGL(centre_convert_kernel<TRAKNN_FP16>, g, dim3(256), 0, s,
-                         X, ldx, T, D, Dpad, mu, xc, norm);
+                         X, ldx, T, D, Tpad, Dpad, mu, xc, ncs);
       break;
   }
   return hipGetLastError();
