@@ -52,9 +52,12 @@ extern "C" {
 #define TRAKNN_ERR_HIP (-4)         /* a HIP runtime call or kernel launch failed */
 
 /* Precision of the Gram contraction (Eq. 4). In every mode the fields are first
- * centred per grid cell in FP64 (distances are translation invariant), squared
- * norms and the epilogue N_i + N_j - 2G are FP64, distances are stored FP32 and
- * trajectory sums (Eq. 2/5) are FP64.
+ * centred per grid cell in FP64 (distances are translation invariant); squared
+ * norms are FP64 sums over chunks of 512 cells of the represented vectors,
+ * which the FP32 Gram accumulators subtract chunk by chunk so that they carry
+ * -d/2 rather than the inner product (rounding errors scale with the distance,
+ * not the norms); distances are stored FP32 and trajectory sums (Eq. 2/5) are
+ * FP64.
  *   TRAKNN_FP32   : centred fields rounded to FP32, FP32 MFMA (32x32x2).
  *   TRAKNN_BF16X3 : centred fields split hi = bf16(x), lo = bf16(x - hi);
  *                   G = hi.hi' + hi.lo' + lo.hi' on BF16 MFMA (32x32x16) with FP32
