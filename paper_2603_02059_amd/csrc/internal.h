@@ -109,7 +109,7 @@ hipError_t launch_backward(const float* X, int64_t ldx, int64_t T, int64_t D,
 size_t window_lds_bytes(int L_max, int NL, int k, int rows);
 size_t window1_lds_bytes(int L, int k, int W);
 #ifndef TRAKNN_WINDOW1_ROWS
-#define TRAKNN_WINDOW1_ROWS 32
+#define TRAKNN_WINDOW1_ROWS 16
 #endif
 constexpr int WINDOW1_ROWS = TRAKNN_WINDOW1_ROWS;  // rows per single-length window wave
 

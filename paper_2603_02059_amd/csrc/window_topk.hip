@@ -306,8 +306,8 @@ __device__ __forceinline__ void seed_row(double d, int c, bool valid, int k, dou
   }
 }
 
-// One workgroup per row block: wave w scans every W-th chunk of 64 diagonals,
-// starting at chunk w, and keeps its own partial lists. The waves also share
+// One workgroup per row block: wave w scans the w-th of W contiguous ranges
+// of 64-diagonal chunks and keeps its own partial lists. The waves also share
 // one distance bound per row in LDS -- the smallest k-th distance any of them
 // has reached -- and skip candidates above it: such a candidate already has k
 // better ones elsewhere, so it cannot be among the row's k nearest
@@ -344,10 +344,7 @@ __global__ __launch_bounds__(1024) void window1_kernel(
   const int nrows = npL - r0 < R ? npL - r0 : R;  // rows of this block
   const int64_t dlo = -(int64_t)(r0 + R - 1);
   const int64_t NC = ((int64_t)npL + R - 1 + 63) / 64;
-  // wave `split` takes chunks split, split + W, ...: the W waves of the block
-  // move along the rows side by side, so together they read W * 256
-  // contiguous bytes of each row at a time
-  const int64_t cb = split, ce = NC;
+  const int64_t cb = (int64_t)split * NC / W, ce = (int64_t)(split + 1) * NC / W;
 
   double thr_d = __builtin_huge_val();  // lane q: own k-th of row r0 + q
   int thr_i = INT_MAX;
@@ -459,14 +456,14 @@ __global__ __launch_bounds__(1024) void window1_kernel(
 
   if (cb < ce) load(cb);
   const bool full = nrows == R;
-  for (int64_t c = cb; c < ce; c += W) {
+  for (int64_t c = cb; c < ce; ++c) {
     // park this chunk's values in this wave's LDS rows (LDS accesses of a
     // wave execute in order), then start fetching the next chunk
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
     for (int m = 0; m < M; ++m) vl[m * 64 + lane] = nxt[m];
     __builtin_amdgcn_wave_barrier();
-    if (c + W < ce) load(c + W);
+    if (c + 1 < ce) load(c + 1);
     const int64_t dc = dlo + 64 * c;
     const bool interior = full & ((dc >= L) | (dc + 63 <= -L)) & (r0 + dc >= 0) &
                           (r0 + R - 1 + dc + 63 < npL);
