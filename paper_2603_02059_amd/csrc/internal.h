@@ -42,7 +42,7 @@ constexpr int WIN_WAVE = 64;
 
 // Per-stage event slots for optional timing.
 constexpr int NUM_STAGES = 5;
-constexpr int COLSTAT_ROWS = 64;  // rows per partial column-sum block
+constexpr int COLSTAT_ROWS = 128;  // rows per partial column-sum block
 
 struct Layout {
   size_t mu_part, mu, ncs, xc, S, part_d, part_i;  // forward

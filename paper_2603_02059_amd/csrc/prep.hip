@@ -18,18 +18,53 @@
 namespace traknn {
 namespace {
 
-// Partial column sums over blocks of COLSTAT_ROWS rows: one thread per cell,
-// a wave reads 64 consecutive floats of a row.
+// Partial column sums over blocks of COLSTAT_ROWS rows: each thread sums 4
+// consecutive cells (one 16-byte load per row, 1 KB per wave and row), eight
+// rows in flight at a time, in a fixed order.
 __global__ __launch_bounds__(256) void colsum_partial_kernel(
     const float* __restrict__ X, int64_t ldx, int64_t T, int64_t D,
     double* __restrict__ part) {
-  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t c = 4 * ((int64_t)blockIdx.x * 256 + threadIdx.x);
   const int64_t r0 = (int64_t)blockIdx.y * COLSTAT_ROWS;
   if (c >= D) return;
   const int64_t r1 = r0 + COLSTAT_ROWS < T ? r0 + COLSTAT_ROWS : T;
-  double s = 0.0;
-  for (int64_t r = r0; r < r1; ++r) s += (double)X[r * ldx + c];
-  part[(int64_t)blockIdx.y * D + c] = s;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  if (c + 4 <= D) {
+    const float* p = X + r0 * ldx + c;
+    int64_t r = r0;
+    for (; r + 8 <= r1; r += 8) {
+      float4 v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = *(const float4*)(p + u * ldx);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        s0 += (double)v[u].x;
+        s1 += (double)v[u].y;
+        s2 += (double)v[u].z;
+        s3 += (double)v[u].w;
+      }
+      p += 8 * ldx;
+    }
+    for (; r < r1; ++r, p += ldx) {
+      const float4 v = *(const float4*)p;
+      s0 += (double)v.x;
+      s1 += (double)v.y;
+      s2 += (double)v.z;
+      s3 += (double)v.w;
+    }
+  } else {
+    for (int64_t r = r0; r < r1; ++r) {
+      const float* p = X + r * ldx + c;
+      s0 += (double)p[0];
+      if (c + 1 < D) s1 += (double)p[1];
+      if (c + 2 < D) s2 += (double)p[2];
+    }
+  }
+  double* out = part + (int64_t)blockIdx.y * D + c;
+  out[0] = s0;
+  if (c + 1 < D) out[1] = s1;
+  if (c + 2 < D) out[2] = s2;
+  if (c + 3 < D) out[3] = s3;
 }
 
 // Fixed-order reduction of the partial sums -> per-cell mean.
@@ -39,6 +74,7 @@ __global__ __launch_bounds__(256) void colsum_reduce_kernel(
   const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (c >= D) return;
   double s = 0.0;
+#pragma unroll 8
   for (int q = 0; q < nchunks; ++q) s += part[(int64_t)q * D + c];
   mu[c] = s / (double)T;
 }
@@ -48,63 +84,113 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
-__device__ inline uint16_t bf16_bits_rne(float f) {
+__device__ inline uint32_t bf16_bits_rne(float f) {
   // round-to-nearest-even of an FP32 value to BF16 (inputs are finite)
   uint32_t u = __float_as_uint(f);
   u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
+  return u >> 16;
 }
-__device__ inline double bf16_bits_to_double(uint16_t b) {
-  return (double)__uint_as_float((uint32_t)b << 16);
+__device__ inline double bf16_bits_to_double(uint32_t b) {
+  return (double)__uint_as_float(b << 16);
 }
 
-// One workgroup of 4 waves per (padded) row; wave w converts the norm chunks
-// w, w + 4, ... of GRAM_CHUNK elements and writes each chunk's squared norm
-// (FP64 sum in a fixed order, stored FP32) to ncs[chunk * Tpad + row]. PREC
-// selects the emitted representation.
+// Wave (blockIdx.x * 4 + w) owns norm chunk ch = that index (GRAM_CHUNK
+// elements; lane q the 8 consecutive elements 8q .. 8q+7) and converts it for
+// CONV_ROWS consecutive rows starting at blockIdx.y * CONV_ROWS, keeping the
+// chunk's means in registers: two 16-byte loads and one or two 16-byte stores
+// per lane and row. Each (row, chunk) squared norm (FP64 sum, stored FP32) goes
+// to ncs[chunk * Tpad + row]. PREC selects the emitted representation.
+constexpr int CONV_ROWS = 16;
 template <int PREC>
 __global__ __launch_bounds__(256) void centre_convert_kernel(
     const float* __restrict__ X, int64_t ldx, int64_t T, int64_t D,
     int64_t Tpad, int64_t Dpad, const double* __restrict__ mu,
     void* __restrict__ xc, float* __restrict__ ncs) {
-  const int64_t i = blockIdx.x;
-  const bool live = i < T;
+  static_assert(GRAM_CHUNK == 64 * 8, "a wave covers one norm chunk");
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int64_t nch = norm_chunks(Dpad);
-  for (int64_t ch = w; ch < nch; ch += 4) {
-    double acc = 0.0;
+  const int64_t ch = (int64_t)blockIdx.x * 4 + w;
+  if (ch >= norm_chunks(Dpad)) return;
+  const int64_t e0 = ch * GRAM_CHUNK + 8 * lane;  // Dpad is a multiple of 8
+  const bool in_pad = e0 < Dpad;
+  const bool full = e0 + 8 <= D;
+  double m[8];
 #pragma unroll
-    for (int m = 0; m < GRAM_CHUNK / 64; ++m) {
-      const int64_t c = ch * GRAM_CHUNK + m * 64 + lane;
-      if (c >= Dpad) break;
-      const double v = (live && c < D) ? (double)X[i * ldx + c] - mu[c] : 0.0;
-      if constexpr (PREC == TRAKNN_FP32) {
-        const float f = (float)v;
-        const double fd = (double)f;
-        acc += fd * fd;
-        ((float*)xc)[i * Dpad + c] = f;
-      } else if constexpr (PREC == TRAKNN_FP16) {
-        const _Float16 h = (_Float16)(float)v;
-        const double hd = (double)(float)h;
-        acc += hd * hd;
-        ((_Float16*)xc)[i * Dpad + c] = h;
+  for (int u = 0; u < 8; ++u) m[u] = e0 + u < D ? mu[e0 + u] : 0.0;
+  for (int rr = 0; rr < CONV_ROWS; ++rr) {
+    const int64_t i = (int64_t)blockIdx.y * CONV_ROWS + rr;
+    if (i >= Tpad) break;
+    const bool live = i < T;
+    const float* xrow = X + i * ldx;
+    double acc = 0.0;
+    if (in_pad) {
+      double v[8];
+      if (live && full) {
+        const float4 a = *(const float4*)(xrow + e0);
+        const float4 b = *(const float4*)(xrow + e0 + 4);
+        v[0] = (double)a.x - m[0];
+        v[1] = (double)a.y - m[1];
+        v[2] = (double)a.z - m[2];
+        v[3] = (double)a.w - m[3];
+        v[4] = (double)b.x - m[4];
+        v[5] = (double)b.y - m[5];
+        v[6] = (double)b.z - m[6];
+        v[7] = (double)b.w - m[7];
       } else {
-        // BF16X3: 16-byte chunks alternate 8 hi values and the 8 matching lo
-        // values, so one 128-byte Gram stage row holds 32 (hi, lo) pairs.
-        const uint16_t hb = bf16_bits_rne((float)v);
-        const double hd = bf16_bits_to_double(hb);
-        const uint16_t lb = bf16_bits_rne((float)(v - hd));
-        const double ld = bf16_bits_to_double(lb);
-        // norm of the represented value hi + lo (exact in FP64). The Gram
-        // stage drops only the cross term lo_i.lo_j, which has zero mean; a
-        // norm made of the three kept products alone would bias every
-        // distance low by sum (lo_i - lo_j)^2 ~ 2.5e-6 (N_i + N_j).
-        const double xv = hd + ld;
-        acc += xv * xv;
-        uint16_t* out = (uint16_t*)xc + i * Dpad * 2;
-        const int64_t chunk = c >> 3, within = c & 7;
-        out[chunk * 16 + within] = hb;
-        out[chunk * 16 + 8 + within] = lb;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int64_t e = e0 + u;
+          v[u] = (live && e < D) ? (double)xrow[e] - m[u] : 0.0;
+        }
+      }
+      if constexpr (PREC == TRAKNN_FP32) {
+        float f[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          f[u] = (float)v[u];
+          acc += (double)f[u] * (double)f[u];
+        }
+        float4* out = (float4*)((float*)xc + i * Dpad + e0);
+        out[0] = make_float4(f[0], f[1], f[2], f[3]);
+        out[1] = make_float4(f[4], f[5], f[6], f[7]);
+      } else if constexpr (PREC == TRAKNN_FP16) {
+        uint32_t packed[4];
+#pragma unroll
+        for (int u = 0; u < 8; u += 2) {
+          const _Float16 h0 = (_Float16)(float)v[u], h1 = (_Float16)(float)v[u + 1];
+          const double d0 = (double)(float)h0, d1 = (double)(float)h1;
+          acc += d0 * d0;
+          acc += d1 * d1;
+          packed[u / 2] = (uint32_t)__builtin_bit_cast(uint16_t, h0) |
+                          ((uint32_t)__builtin_bit_cast(uint16_t, h1) << 16);
+        }
+        *(uint4*)((_Float16*)xc + i * Dpad + e0) =
+            make_uint4(packed[0], packed[1], packed[2], packed[3]);
+      } else {
+        // BF16X3: the 16-byte chunk of 8 hi values is followed by the chunk of
+        // the 8 matching lo values, so one 128-byte Gram stage row holds 32
+        // (hi, lo) pairs.
+        uint32_t hp[4], lp[4];
+#pragma unroll
+        for (int u = 0; u < 8; u += 2) {
+          uint32_t hb[2], lb[2];
+#pragma unroll
+          for (int t = 0; t < 2; ++t) {
+            hb[t] = bf16_bits_rne((float)v[u + t]);
+            const double hd = bf16_bits_to_double(hb[t]);
+            lb[t] = bf16_bits_rne((float)(v[u + t] - hd));
+            // norm of the represented value hi + lo (exact in FP64). The Gram
+            // stage drops only the cross term lo_i.lo_j, which has zero mean;
+            // a norm made of the three kept products alone would bias every
+            // distance low by sum (lo_i - lo_j)^2 ~ 2.5e-6 (N_i + N_j).
+            const double xv = hd + bf16_bits_to_double(lb[t]);
+            acc += xv * xv;
+          }
+          hp[u / 2] = hb[0] | (hb[1] << 16);
+          lp[u / 2] = lb[0] | (lb[1] << 16);
+        }
+        uint4* out = (uint4*)((uint16_t*)xc + i * Dpad * 2 + 2 * e0);
+        out[0] = make_uint4(hp[0], hp[1], hp[2], hp[3]);
+        out[1] = make_uint4(lp[0], lp[1], lp[2], lp[3]);
       }
     }
     acc = wave_sum(acc);
@@ -117,7 +203,7 @@ __global__ __launch_bounds__(256) void centre_convert_kernel(
 hipError_t launch_colstats(const float* X, int64_t ldx, int64_t T, int64_t D,
                            int tchunks, double* mu_part, double* mu,
                            hipStream_t s) {
-  dim3 g1((unsigned)((D + 255) / 256), (unsigned)tchunks);
+  dim3 g1((unsigned)((D + 1023) / 1024), (unsigned)tchunks);
   hipLaunchKernelGGL(colsum_partial_kernel, g1, dim3(256), 0, s, X, ldx, T, D,
                      mu_part);
   hipError_t e = hipGetLastError();
@@ -131,7 +217,7 @@ hipError_t launch_centre_convert(const float* X, int64_t ldx, int64_t T,
                                  int64_t D, int64_t Tpad, int64_t Dpad,
                                  int precision, const double* mu, void* xc,
                                  float* ncs, hipStream_t s) {
-  dim3 g((unsigned)Tpad);
+  dim3 g((unsigned)((norm_chunks(Dpad) + 3) / 4), (unsigned)((Tpad + CONV_ROWS - 1) / CONV_ROWS));
   switch (precision) {
     case TRAKNN_FP32:
       hipLaunchKernelGGL(centre_convert_kernel<TRAKNN_FP32>, g, dim3(256), 0, s,
