@@ -104,7 +104,9 @@ typedef struct traknn_plan_s* traknn_plan_t;
  *   workspace_bytes  [out] device bytes the caller must provide to traknn_knn
  *                          and traknn_score_backward (one size covers both).
  * Errors: INVALID_ARG for NULL pointers or sizes out of range; UNSUPPORTED for
- * row_batch != 0 or a multi-length sweep with L_min != 1. */
+ * row_batch != 0, a multi-length sweep with L_min != 1, or a D whose 256-field
+ * Gram operand panel would reach 2 GiB (D >= 2^21 for FP32 and BF16X3,
+ * D >= 2^22 for FP16). */
 int traknn_plan(const traknn_config* cfg, traknn_plan_t* out,
                 size_t* workspace_bytes);
 

@@ -163,6 +163,10 @@ int traknn_plan(const traknn_config* cfg, traknn_plan_t* out,
     return TRAKNN_ERR_INVALID_ARG;
   if (c.row_batch != 0) return TRAKNN_ERR_UNSUPPORTED;
   if (c.L_min != c.L_max && c.L_min != 1) return TRAKNN_ERR_UNSUPPORTED;
+  // the Gram stage addresses a 256-field operand panel with 32-bit offsets
+  if ((uint64_t)round_up(c.D, stage_k(c.precision)) * elem_bytes(c.precision) * GRAM_TILE >
+      0x7FFFFFFFull)
+    return TRAKNN_ERR_UNSUPPORTED;
 
   traknn_plan_s* p = new (std::nothrow) traknn_plan_s();
   if (!p) return TRAKNN_ERR_INVALID_ARG;

@@ -25,6 +25,8 @@
 // ids round-robin to the 8 XCDs, so each XCD is handed a contiguous run of a
 // grouped tile order (4 block-rows x successive block-columns). The ~32 tiles
 // an XCD runs at once then share 4 A panels and ~8 B panels in its L2.
+#include <type_traits>
+
 #include "internal.h"
 
 namespace traknn {
@@ -54,11 +56,12 @@ static_assert((GRAM_THREADS / 64) * (TILE / (GRAM_THREADS / 64 / 2)) * EPI_PITCH
 constexpr int NORM_LDS = 2 * 2 * TILE * 4;  // two chunks' norms of the I and J rows
 
 // Physical 16-byte slot of logical chunk `chunk` in LDS row `row`. The XOR key
-// (row ^ row>>3) & 7 makes any 8 aligned consecutive rows use 8 distinct
-// slots and any 16 aligned consecutive rows use 16 distinct (row parity,
-// slot) pairs, so ds_read_b128 of 32 consecutive rows is conflict-free
-// whether the LDS serves 8 lanes over 32 banks or 16 lanes over 64 banks.
-__device__ __forceinline__ int swz_key(int row) { return (row ^ (row >> 3)) & 7; }
+// (row & 7) ^ ((row >> 3) & 3) gives any 8 aligned consecutive rows 8
+// distinct slots, any 16 aligned rows 16 distinct (row parity, slot) pairs and
+// any 32 aligned rows 32 distinct (row mod 4, slot) pairs, so ds_read_b128 of
+// 32 consecutive rows is conflict-free whether the LDS serves 8, 16 or 32
+// lanes per pass. It ignores row bits 5 and up, so rows 32 apart share a key.
+__device__ __forceinline__ int swz_key(int row) { return (row & 7) ^ ((row >> 3) & 3); }
 __device__ __forceinline__ int swz(int row, int chunk) {
   return ((chunk ^ swz_key(row)) << 4);
 }
@@ -97,117 +100,112 @@ __device__ __forceinline__ bool decode_tile(int64_t wg, int nb, int64_t ntiles,
 constexpr int SG_MFMA = 0x008;
 constexpr int SG_DS_READ = 0x100;
 
-// Read/MFMA counts per k-slice and slices per stage for each precision.
+// Operand fragments of half a K stage for one wave: two 16-byte chunks of
+// each of the wave's 128 A rows and 64 B rows. Lane half h (lanes 32h ..
+// 32h+31) supplies k-group h of every MFMA; A and B use the same assignment,
+// so which elements a group holds does not matter. Part p of a stage:
+//   BF16x3: the 16 (hi, lo) pairs of k-slice p: x0/y0 = hi (chunk 4p + 2h),
+//           x1/y1 = lo (chunk 4p + 2h + 1); MFMAs hi.hi', hi.lo', lo.hi'.
+//   FP16:   k-slices 2p, 2p+1 (chunks 4p + h, 4p + 2 + h), one MFMA each.
+//   FP32:   chunks 4p + h, 4p + 2 + h, four depth-2 MFMAs each.
 template <int PREC>
-struct SliceShape {
-  static constexpr int slices = PREC == TRAKNN_BF16X3 ? 2 : 4;
-  static constexpr int reads = PREC == TRAKNN_BF16X3 ? 2 * (BM + BN) : (BM + BN);
-  static constexpr int mfmas = PREC == TRAKNN_BF16X3 ? 3 * BM * BN
-                               : PREC == TRAKNN_FP16 ? BM * BN : 4 * BM * BN;
+struct Part {
+  using V = typename std::conditional<PREC == TRAKNN_BF16X3, bf16x8,
+            typename std::conditional<PREC == TRAKNN_FP16, f16x8, f32x4>::type>::type;
+  V x0[BM], x1[BM], y0[BN], y1[BN];
 };
-
-// One K stage of MFMAs on the LDS operand tiles A (rows of the I block) and B
-// (rows of the J block). The first k-slice's fragments are read up front; the
-// reads of each later slice are spread over the MFMAs of the earlier slices so
-// only the first slice's LDS latency is exposed.
+constexpr int PART_READS = 2 * (BM + BN);
 template <int PREC>
-__device__ __forceinline__ void compute_stage(const char* __restrict__ A,
-                                              const char* __restrict__ B,
-                                              int wm, int wn, int lane,
-                                              f32x16 (&acc)[BM][BN]) {
-  using SS = SliceShape<PREC>;
-  const int r32 = lane & 31;
-  const int half = lane >> 5;
+constexpr int part_mfmas() {
+  return PREC == TRAKNN_BF16X3 ? 3 * BM * BN : PREC == TRAKNN_FP16 ? 2 * BM * BN : 8 * BM * BN;
+}
+
+// Lane offsets of a part's two chunks in the A and B tiles of a stage buffer.
+// The wave's rows wm*WT_M + q*32 + r32 (A) and wn*WT_N + q*32 + r32 (B) share
+// the swizzle key of r32, so q is an immediate offset of q * 32 rows.
+struct PartOffsets {
+  int a0, a1, b0, b1;
+};
+template <int PREC>
+__device__ __forceinline__ PartOffsets part_offsets(int p, int wm, int wn, int lane) {
+  const int r32 = lane & 31, h = lane >> 5;
+  const int key = swz_key(r32);
+  const int c0 = 4 * p + (PREC == TRAKNN_BF16X3 ? 2 * h : h);
+  const int c1 = c0 + (PREC == TRAKNN_BF16X3 ? 1 : 2);
+  PartOffsets o;
+  o.a0 = (wm * WT_M + r32) * RB + ((c0 ^ key) << 4);
+  o.a1 = (wm * WT_M + r32) * RB + ((c1 ^ key) << 4);
+  o.b0 = OPER_BYTES + (wn * WT_N + r32) * RB + ((c0 ^ key) << 4);
+  o.b1 = OPER_BYTES + (wn * WT_N + r32) * RB + ((c1 ^ key) << 4);
+  return o;
+}
+
+template <int PREC>
+__device__ __forceinline__ void read_part(const char* __restrict__ buf, const PartOffsets& o,
+                                          Part<PREC>& P) {
+  using V = typename Part<PREC>::V;
+#pragma unroll
+  for (int q = 0; q < BM; ++q) {
+    P.x0[q] = *(const V*)(buf + o.a0 + q * 32 * RB);
+    P.x1[q] = *(const V*)(buf + o.a1 + q * 32 * RB);
+  }
+#pragma unroll
+  for (int q = 0; q < BN; ++q) {
+    P.y0[q] = *(const V*)(buf + o.b0 + q * 32 * RB);
+    P.y1[q] = *(const V*)(buf + o.b1 + q * 32 * RB);
+  }
+}
+
+template <int PREC>
+__device__ __forceinline__ void mfma_part(const Part<PREC>& P, f32x16 (&acc)[BM][BN]) {
   if constexpr (PREC == TRAKNN_BF16X3) {
-    bf16x8 ah[2][BM], al[2][BM], bh[2][BN], bl[2][BN];
 #pragma unroll
-    for (int kk = 0; kk < 2; ++kk) {
-      const int g = 2 * kk + half;  // 8-element group this lane supplies
+    for (int bm = 0; bm < BM; ++bm)
 #pragma unroll
-      for (int q = 0; q < BM; ++q) {
-        const int ra = wm * WT_M + q * 32 + r32;
-        ah[kk][q] = *(const bf16x8*)(A + ra * RB + swz(ra, 2 * g));
-        al[kk][q] = *(const bf16x8*)(A + ra * RB + swz(ra, 2 * g + 1));
+      for (int bn = 0; bn < BN; ++bn) {
+        acc[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(P.x0[bm], P.y0[bn], acc[bm][bn], 0, 0, 0);
+        acc[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(P.x0[bm], P.y1[bn], acc[bm][bn], 0, 0, 0);
+        acc[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(P.x1[bm], P.y0[bn], acc[bm][bn], 0, 0, 0);
       }
-#pragma unroll
-      for (int q = 0; q < BN; ++q) {
-        const int rb = wn * WT_N + q * 32 + r32;
-        bh[kk][q] = *(const bf16x8*)(B + rb * RB + swz(rb, 2 * g));
-        bl[kk][q] = *(const bf16x8*)(B + rb * RB + swz(rb, 2 * g + 1));
-      }
-    }
-#pragma unroll
-    for (int kk = 0; kk < 2; ++kk)
-#pragma unroll
-      for (int bm = 0; bm < BM; ++bm)
-#pragma unroll
-        for (int bn = 0; bn < BN; ++bn) {
-          acc[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[kk][bm], bh[kk][bn], acc[bm][bn], 0, 0, 0);
-          acc[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[kk][bm], bl[kk][bn], acc[bm][bn], 0, 0, 0);
-          acc[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[kk][bm], bh[kk][bn], acc[bm][bn], 0, 0, 0);
-        }
   } else if constexpr (PREC == TRAKNN_FP16) {
-    f16x8 a[4][BM], b[4][BN];
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
-      const int g = 2 * kk + half;
+    for (int bm = 0; bm < BM; ++bm)
 #pragma unroll
-      for (int q = 0; q < BM; ++q) {
-        const int ra = wm * WT_M + q * 32 + r32;
-        a[kk][q] = *(const f16x8*)(A + ra * RB + swz(ra, g));
-      }
+      for (int bn = 0; bn < BN; ++bn)
+        acc[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_f16(P.x0[bm], P.y0[bn], acc[bm][bn], 0, 0, 0);
 #pragma unroll
-      for (int q = 0; q < BN; ++q) {
-        const int rb = wn * WT_N + q * 32 + r32;
-        b[kk][q] = *(const f16x8*)(B + rb * RB + swz(rb, g));
-      }
-    }
+    for (int bm = 0; bm < BM; ++bm)
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk)
+      for (int bn = 0; bn < BN; ++bn)
+        acc[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_f16(P.x1[bm], P.y1[bn], acc[bm][bn], 0, 0, 0);
+  } else {
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
 #pragma unroll
       for (int bm = 0; bm < BM; ++bm)
 #pragma unroll
         for (int bn = 0; bn < BN; ++bn)
-          acc[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a[kk][bm], b[kk][bn], acc[bm][bn], 0, 0, 0);
-  } else {
-    // FP32: each lane reads 4 consecutive k of chunk 2s + half; MFMA e of the
-    // four consumes element e, so the 4 MFMAs x 2 lane halves cover 8 k.
-    f32x4 a[4][BM], b[4][BN];
+          acc[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x2f32(P.x0[bm][e], P.y0[bn][e], acc[bm][bn], 0, 0, 0);
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int c = 2 * s + half;
+    for (int e = 0; e < 4; ++e)
 #pragma unroll
-      for (int q = 0; q < BM; ++q) {
-        const int ra = wm * WT_M + q * 32 + r32;
-        a[s][q] = *(const f32x4*)(A + ra * RB + swz(ra, c));
-      }
+      for (int bm = 0; bm < BM; ++bm)
 #pragma unroll
-      for (int q = 0; q < BN; ++q) {
-        const int rb = wn * WT_N + q * 32 + r32;
-        b[s][q] = *(const f32x4*)(B + rb * RB + swz(rb, c));
-      }
-    }
-#pragma unroll
-    for (int s = 0; s < 4; ++s)
-#pragma unroll
-      for (int e = 0; e < 4; ++e)
-#pragma unroll
-        for (int bm = 0; bm < BM; ++bm)
-#pragma unroll
-          for (int bn = 0; bn < BN; ++bn)
-            acc[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[s][bm][e], b[s][bn][e], acc[bm][bn], 0, 0, 0);
+        for (int bn = 0; bn < BN; ++bn)
+          acc[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x2f32(P.x1[bm][e], P.y1[bn][e], acc[bm][bn], 0, 0, 0);
   }
-  // first slice's reads | (q MFMA, 1 read) for every later read | the rest
-  constexpr int later_reads = (SS::slices - 1) * SS::reads;
-  constexpr int q = SS::mfmas / SS::reads;
-#pragma unroll
-  for (int i = 0; i < SS::reads; ++i) __builtin_amdgcn_sched_group_barrier(SG_DS_READ, 1, 0);
-#pragma unroll
-  for (int i = 0; i < later_reads; ++i) {
-    __builtin_amdgcn_sched_group_barrier(SG_MFMA, q, 0);
+}
+
+// Spread PART_READS reads over MF MFMAs: read i is followed by the MFMAs that
+// bring the running count to floor((i + 1) * MF / PART_READS).
+template <int MF, int I = 0>
+__device__ __forceinline__ void interleave_reads() {
+  if constexpr (I < PART_READS) {
     __builtin_amdgcn_sched_group_barrier(SG_DS_READ, 1, 0);
+    constexpr int n = (I + 1) * MF / PART_READS - I * MF / PART_READS;
+    if constexpr (n > 0) __builtin_amdgcn_sched_group_barrier(SG_MFMA, n, 0);
+    interleave_reads<MF, I + 1>();
   }
-  __builtin_amdgcn_sched_group_barrier(SG_MFMA, SS::slices * SS::mfmas - later_reads * q, 0);
 }
 
 template <int PREC>
@@ -226,21 +224,36 @@ __global__ __launch_bounds__(GRAM_THREADS, 1) void gram_kernel(
   const char* Ag = xc + (int64_t)I * TILE * pitch;
   const char* Bg = xc + (int64_t)J * TILE * pitch;
 
-  // Direct global -> LDS loads (gfx950 global_load_lds_dwordx4): lane q of a
-  // load lands at byte 16*q of the wave's 1 KB destination block, so each lane
+  // Direct buffer -> LDS loads (buffer_load_dwordx4 ... lds): lane q of a load
+  // lands at byte 16*q of the wave's 1 KB destination block, so each lane
   // fetches the logical chunk whose swizzled slot is that destination. Each
   // wave moves 8 KB of A and 8 KB of B per stage and no VGPR stages the data.
+  // The buffer resources span the two 256-row panels (the planner keeps a
+  // panel below 4 GiB), so a lane needs one 32-bit offset per block, shared by
+  // A and B, and the stage offset travels in the scalar offset.
   constexpr int BLK_PER_WAVE = OPER_BYTES / 1024 / (GRAM_THREADS / 64);
+  constexpr int RSRC_WORD3 = 0x00020000;  // raw 32-bit buffer, gfx9 family
+  const int panel_bytes = (int)(uint32_t)(TILE * pitch);
+  const __amdgpu_buffer_rsrc_t rsA = __builtin_amdgcn_make_buffer_rsrc((void*)Ag, 0, panel_bytes, RSRC_WORD3);
+  const __amdgpu_buffer_rsrc_t rsB = __builtin_amdgcn_make_buffer_rsrc((void*)Bg, 0, panel_bytes, RSRC_WORD3);
+  uint32_t voff[BLK_PER_WAVE];
+#pragma unroll
+  for (int u = 0; u < BLK_PER_WAVE; ++u) {
+    const int row = (w * BLK_PER_WAVE + u) * 8 + (lane >> 3);
+    const int c = (lane & 7) ^ swz_key(row);  // inverse of swz
+    voff[u] = (uint32_t)row * (uint32_t)pitch + (uint32_t)(c * 16);
+  }
   auto issue = [&](int st, int buf) {
     char* A = lds + buf * 2 * OPER_BYTES;
+    const uint32_t soff = (uint32_t)st * RB;
 #pragma unroll
     for (int u = 0; u < BLK_PER_WAVE; ++u) {
-      const int blk = w * BLK_PER_WAVE + u;    // 1 KB block
-      const int row = blk * 8 + (lane >> 3);
-      const int c = (lane & 7) ^ swz_key(row);  // inverse of swz
-      const int64_t off = (int64_t)row * pitch + (int64_t)st * RB + c * 16;
-      __builtin_amdgcn_global_load_lds(Ag + off, A + blk * 1024, 16, 0, 0);
-      __builtin_amdgcn_global_load_lds(Bg + off, A + OPER_BYTES + blk * 1024, 16, 0, 0);
+      const int blk = w * BLK_PER_WAVE + u;  // 1 KB block
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(
+          rsA, (__attribute__((address_space(3))) void*)(A + blk * 1024), 16, voff[u], soff, 0, 0);
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(
+          rsB, (__attribute__((address_space(3))) void*)(A + OPER_BYTES + blk * 1024), 16, voff[u],
+          soff, 0, 0);
     }
   };
 
@@ -285,22 +298,46 @@ __global__ __launch_bounds__(GRAM_THREADS, 1) void gram_kernel(
   };
   constexpr int SPC = GRAM_CHUNK / (PREC == TRAKNN_FP16 ? 64 : 32);  // stages per chunk
 
+  // Every stage is two parts. Part 0 of stage st is read while the MFMAs of
+  // part 1 of stage st - 1 run (right after the barrier that makes stage st
+  // visible), part 1 of st while the MFMAs of part 0 of st run; so LDS read
+  // latency hides behind MFMAs and only one part's fragments are in flight.
+  const PartOffsets o0 = part_offsets<PREC>(0, wm, wn, lane);
+  const PartOffsets o1 = part_offsets<PREC>(1, wm, wn, lane);
+  Part<PREC> P0, P1;
   issue(0, 0);
+  if (nstages == 1 && w < 2) issue_norms(0);
   __builtin_amdgcn_s_waitcnt(VMCNT0);
   __syncthreads();
-  for (int st = 0; st < nstages; ++st) {
+  read_part<PREC>(lds, o0, P0);
+  for (int st = 0; st + 1 < nstages; ++st) {
     const int buf = st & 1;
-    const bool more = st + 1 < nstages;
     const int ch = st / SPC;
-    const bool chunk_end = !more || (st + 1) % SPC == 0;
-    if (more) issue(st + 1, buf ^ 1);
-    if (chunk_end && w < 2) issue_norms(ch);
-    const char* A = lds + buf * 2 * OPER_BYTES;
-    compute_stage<PREC>(A, A + OPER_BYTES, wm, wn, lane, acc);
+    const bool chunk_end = (st + 1) % SPC == 0;
+    issue(st + 1, buf ^ 1);
+    // the norms of the chunk that ends at stage st + 1 ride with its loads
+    if ((st + 2 == nstages || (st + 2) % SPC == 0) && w < 2) issue_norms((st + 1) / SPC);
+    read_part<PREC>(lds + buf * 2 * OPER_BYTES, o1, P1);
+    mfma_part<PREC>(P0, acc);
+    interleave_reads<part_mfmas<PREC>()>();
+    __builtin_amdgcn_sched_barrier(0);
     __builtin_amdgcn_s_waitcnt(VMCNT0);
     __syncthreads();
+    __builtin_amdgcn_sched_barrier(0);
+    read_part<PREC>(lds + (buf ^ 1) * 2 * OPER_BYTES, o0, P0);
+    mfma_part<PREC>(P1, acc);
+    interleave_reads<part_mfmas<PREC>()>();
+    __builtin_amdgcn_sched_barrier(0);
     if (chunk_end) correct(ch);
   }
+  {  // last stage: nothing left to fetch
+    const int st = nstages - 1;
+    read_part<PREC>(lds + (st & 1) * 2 * OPER_BYTES, o1, P1);
+    mfma_part<PREC>(P0, acc);
+    mfma_part<PREC>(P1, acc);
+    correct(st / SPC);
+  }
+  __syncthreads();  // every wave is done with the operand buffers
 
   // Epilogue through LDS (the operand buffers are free now): d = -2 acc.
   // Accumulator r of

@@ -59,6 +59,8 @@ def _plan_code(**kw):
     # n' = T - L + 1 must leave k candidates beyond the exclusion zone
     (dict(T=6, D=1, L_min=2, L_max=2, k=2), 0), (dict(T=6, D=1, L_min=2, L_max=2, k=3), -1),
     (dict(T=9, D=4, L_min=1, L_max=1, k=8), 0), (dict(T=9, D=4, L_min=1, L_max=1, k=9), -1),
+    # a 256-field Gram operand panel must stay below 2 GiB (32-bit buffer offsets)
+    (dict(D=(1 << 21) - 32), 0), (dict(D=1 << 21), -2), (dict(D=1 << 21, precision=2), 0),
 ])
 def test_plan_validation(kw, code):
     assert _plan_code(**kw)[0] == code
