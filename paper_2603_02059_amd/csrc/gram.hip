@@ -49,6 +49,8 @@ constexpr int BM = WT_M / 32, BN = WT_N / 32;  // MFMA blocks per wave
 static_assert(WT_M == 128, "the epilogue parks 32-row bands of 128-row wave tiles");
 // s_waitcnt immediate waiting for vmcnt == 0 only (expcnt, lgkmcnt at max)
 constexpr int VMCNT0 = 0x0F70;
+// vmcnt <= 8 (expcnt, lgkmcnt at max)
+constexpr int VMCNT_LE8 = 0x0F78;
 constexpr int EPI_PITCH = 36;  // floats per parked accumulator column (32 + 4)
 static_assert((GRAM_THREADS / 64) * (TILE / (GRAM_THREADS / 64 / 2)) * EPI_PITCH * 4 <=
                   GRAM_STAGES * 2 * TILE * RB,
@@ -304,26 +306,36 @@ __global__ __launch_bounds__(GRAM_THREADS, 1) void gram_kernel(
   // latency hides behind MFMAs and only one part's fragments are in flight.
   const PartOffsets o0 = part_offsets<PREC>(0, wm, wn, lane);
   const PartOffsets o1 = part_offsets<PREC>(1, wm, wn, lane);
+  // Stage st + 2 is issued right after the barrier in the middle of stage st
+  // (its buffer, that of stage st, has then been read by every wave), so the
+  // loads have the second half of st and the first half of st + 1 to land.
+  // The norms of a chunk travel with the loads of the chunk's last stage.
+  auto issue_stage = [&](int st) {
+    issue(st, st & 1);
+    if ((st + 1 == nstages || (st + 1) % SPC == 0) && w < 2) issue_norms(st / SPC);
+  };
   Part<PREC> P0, P1;
-  issue(0, 0);
-  if (nstages == 1 && w < 2) issue_norms(0);
-  __builtin_amdgcn_s_waitcnt(VMCNT0);
+  issue_stage(0);
+  if (nstages > 1) {
+    issue_stage(1);
+    __builtin_amdgcn_s_waitcnt(VMCNT_LE8);  // stage 0 has landed
+  } else {
+    __builtin_amdgcn_s_waitcnt(VMCNT0);
+  }
   __syncthreads();
   read_part<PREC>(lds, o0, P0);
   for (int st = 0; st + 1 < nstages; ++st) {
     const int buf = st & 1;
     const int ch = st / SPC;
     const bool chunk_end = (st + 1) % SPC == 0;
-    issue(st + 1, buf ^ 1);
-    // the norms of the chunk that ends at stage st + 1 ride with its loads
-    if ((st + 2 == nstages || (st + 2) % SPC == 0) && w < 2) issue_norms((st + 1) / SPC);
     read_part<PREC>(lds + buf * 2 * OPER_BYTES, o1, P1);
     mfma_part<PREC>(P0, acc);
     interleave_reads<part_mfmas<PREC>()>();
     __builtin_amdgcn_sched_barrier(0);
-    __builtin_amdgcn_s_waitcnt(VMCNT0);
+    __builtin_amdgcn_s_waitcnt(VMCNT0);  // stage st + 1 (the only loads in flight)
     __syncthreads();
     __builtin_amdgcn_sched_barrier(0);
+    if (st + 2 < nstages) issue_stage(st + 2);
     read_part<PREC>(lds + (buf ^ 1) * 2 * OPER_BYTES, o0, P0);
     mfma_part<PREC>(P1, acc);
     interleave_reads<part_mfmas<PREC>()>();
