@@ -221,7 +221,8 @@ __global__ __launch_bounds__(GRAM_THREADS, 1) void gram_kernel(
   if (!decode_tile(blockIdx.x, nb, ntiles, I, J)) return;
 
   const int tid = threadIdx.x;
-  const int lane = tid & 63, w = tid >> 6;
+  const int lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
   const int wm = w / WAVES_N, wn = w % WAVES_N;
   const char* Ag = xc + (int64_t)I * TILE * pitch;
   const char* Bg = xc + (int64_t)J * TILE * pitch;
