@@ -198,15 +198,18 @@ __device__ __forceinline__ void mfma_part(const Part<PREC>& P, f32x16 (&acc)[BM]
   }
 }
 
-// Spread PART_READS reads over MF MFMAs: read i is followed by the MFMAs that
-// bring the running count to floor((i + 1) * MF / PART_READS).
+// Interleave a part's PART_READS reads with MF MFMAs: one MFMA, then two reads
+// per MFMA, then the remaining MFMAs, so the reads are done well before the
+// fragments are needed.
 template <int MF, int I = 0>
 __device__ __forceinline__ void interleave_reads() {
+  if constexpr (I == 0) __builtin_amdgcn_sched_group_barrier(SG_MFMA, 1, 0);
   if constexpr (I < PART_READS) {
-    __builtin_amdgcn_sched_group_barrier(SG_DS_READ, 1, 0);
-    constexpr int n = (I + 1) * MF / PART_READS - I * MF / PART_READS;
-    if constexpr (n > 0) __builtin_amdgcn_sched_group_barrier(SG_MFMA, n, 0);
-    interleave_reads<MF, I + 1>();
+    __builtin_amdgcn_sched_group_barrier(SG_DS_READ, 2, 0);
+    __builtin_amdgcn_sched_group_barrier(SG_MFMA, 1, 0);
+    interleave_reads<MF, I + 2>();
+  } else {
+    __builtin_amdgcn_sched_group_barrier(SG_MFMA, MF - 1 - PART_READS / 2, 0);
   }
 }
 
