@@ -67,6 +67,15 @@ def gram_flops(T: int, D: int, prec: str) -> float:
     return passes * 2.0 * D * T * (T + 1) / 2.0
 
 
+def window_bytes(T: int, L: int, rows: int = 16) -> dict:
+    """Bytes of S the window/top-k stage must read: the algorithmic figure is
+    the upper triangle once (4 T(T+1)/2 B); this design reads every row of S
+    (both triangles, so each row's candidates are contiguous) plus the L - 1
+    halo rows of each block of `rows` rows."""
+    return {"algorithmic_bytes": 4.0 * T * (T + 1) / 2,
+            "design_bytes": 4.0 * T * T * (rows + L - 1) / rows}
+
+
 def time_path(tk, torch, X, w, prec, steps, warmup):
     p = tk.Plan(w.T, w.D, w.L, w.L, w.k, prec)
     idx, dist = p.empty_outputs()
@@ -213,6 +222,12 @@ def main():
     gram_ms = head["stage_ms"]["gram"]
     achieved = gram_flops(w.T, w.D, hp) / (gram_ms * 1e-3) / 1e12
     traffic = read_traffic() if hp == "bf16x3" and w.name == "full" else None
+    wb = window_bytes(w.T, w.L)
+    win_ms = head["stage_ms"]["window_topk"]
+    window_hbm = {"kernel": f"window1_kernel<{w.L}>", "avg_launch_ms": win_ms,
+                  "algorithmic_GBps": wb["algorithmic_bytes"] / (win_ms * 1e-3) / 1e9,
+                  "design_GBps": wb["design_bytes"] / (win_ms * 1e-3) / 1e9,
+                  "peak_GBps": HBM_PEAK_GBS, **wb}
     line = {
         "metric": "trajectory pairs/sec at T=27394,D=8192,L=5,k=10; Gram MFMA util vs FP32 path",
         "value": head["pairs_per_s"],
@@ -243,6 +258,7 @@ def main():
                       "gram_mfma_frac": r["gram_tflops"] / PEAKS_TFLOPS[p],
                       "gram_fp32_equiv_tflops": r["gram_fp32_equiv_tflops"]}
                   for p, r in results.items()},
+        "window_hbm": window_hbm,
         "parity_sample": par,
         "planted_in_top40": f"{planted_found}/{len(starts)}",
     }
