@@ -29,51 +29,26 @@ bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
 int fail_hip(hipError_t e) { return e == hipSuccess ? TRAKNN_OK : TRAKNN_ERR_HIP; }
 
-// Choose rows per window wave and column splits. R = 32 keeps the diagonal
-// chunk's LDS staging and list storage small; R = 4 serves large k * NL (up to
-// 16 lengths x 64 neighbours).
-//
-// A single length runs one workgroup of W waves per block of WINDOW1_ROWS rows
-// (the waves split the row block's diagonals and share a per-row bound), with
-// W as large as the LDS budget and the target parallelism allow.
+// Column splits of the window stage: one workgroup of W waves per block of
+// WINDOW1_ROWS rows (the waves split the block's diagonals and share a per-row
+// bound), with W as large as the LDS budget and the target parallelism allow.
+// A multi-length request runs the same kernel once per length; L_max sizes
+// the LDS and the rows of the shortest length size the grid.
 bool plan_window(traknn_plan_s* p) {
   const int k = p->cfg.k;
-  if (p->NL == 1) {
-    const int L = p->cfg.L_max;
-    const int64_t nrb = (p->np0 + WINDOW1_ROWS - 1) / WINDOW1_ROWS;
-    const int64_t nchunks = (p->np0 + WINDOW1_ROWS - 1 + 63) / 64;
-    const size_t base = window1_lds_bytes(L, k, 0);
-    const size_t per_wave = window1_lds_bytes(L, k, 1) - base;
-    if (base + per_wave > MAX_WIN_LDS) return false;
-    int64_t W = (WIN_TARGET_UNITS + nrb - 1) / nrb;
-    const int64_t wmax = (int64_t)((MAX_WIN_LDS - base) / per_wave);
-    if (W > wmax) W = wmax;
-    if (W > MAX_SPLITS) W = MAX_SPLITS;
-    if (W > nchunks) W = nchunks;
-    if (W < 1) W = 1;
-    p->win_rows = WINDOW1_ROWS;
-    p->win_splits = (int)W;
-    p->win_units = nrb * W;
-    p->win_lds = window1_lds_bytes(L, k, (int)W);
-    return true;
-  }
-  int rows = 32;
-  size_t lds = window_lds_bytes(p->cfg.L_max, p->NL, k, rows);
-  if (lds > MAX_WIN_LDS) {
-    rows = 4;
-    lds = window_lds_bytes(p->cfg.L_max, p->NL, k, rows);
-    if (lds > MAX_WIN_LDS) return false;
-  }
-  const int64_t nrb = (p->np0 + rows - 1) / rows;
-  const int64_t nchunks = (p->np0 + rows - 1 + 63) / 64;
+  const int L = p->cfg.L_max;
+  const int64_t nrb = (p->np0 + WINDOW1_ROWS - 1) / WINDOW1_ROWS;
+  const int64_t nchunks = (p->np0 + WINDOW1_ROWS - 1 + 63) / 64;
+  const size_t base = window1_lds_bytes(L, k, 0);
+  const size_t per_wave = window1_lds_bytes(L, k, 1) - base;
+  if (base + per_wave > MAX_WIN_LDS) return false;
   int64_t W = (WIN_TARGET_UNITS + nrb - 1) / nrb;
+  const int64_t wmax = (int64_t)((MAX_WIN_LDS - base) / per_wave);
+  if (W > wmax) W = wmax;
   if (W > MAX_SPLITS) W = MAX_SPLITS;
   if (W > nchunks) W = nchunks;
   if (W < 1) W = 1;
-  p->win_rows = rows;
   p->win_splits = (int)W;
-  p->win_units = nrb * W;
-  p->win_lds = lds;
   return true;
 }
 
@@ -265,8 +240,7 @@ int traknn_knn(traknn_plan_t plan, const float* X, int64_t ldx, void* workspace,
     return rc;
   if ((rc = record(plan, 3, s))) return rc;
   if ((rc = fail_hip(launch_window_topk(S, plan->ldS, plan->T, c.L_min, c.L_max,
-                                        c.k, plan->win_rows, plan->win_splits,
-                                        plan->win_units, plan->win_lds, part_d,
+                                        c.k, plan->win_splits, part_d,
                                         part_i, s))))
     return rc;
   if ((rc = record(plan, 4, s))) return rc;

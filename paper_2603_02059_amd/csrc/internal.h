@@ -35,11 +35,6 @@ inline int elem_bytes(int precision) { return precision == TRAKNN_FP16 ? 2 : 4; 
 constexpr int GRAM_CHUNK = 512;
 __host__ __device__ inline int64_t norm_chunks(int64_t Dpad) { return (Dpad + GRAM_CHUNK - 1) / GRAM_CHUNK; }
 
-// ---------------------------------------------------------------------------
-// Window / top-k stage.
-// ---------------------------------------------------------------------------
-constexpr int WIN_WAVE = 64;
-
 // Per-stage event slots for optional timing.
 constexpr int NUM_STAGES = 5;
 constexpr int COLSTAT_ROWS = 128;  // rows per partial column-sum block
@@ -63,10 +58,7 @@ struct traknn_plan_s {
   int nb;            // Tpad / GRAM_TILE
   int64_t ntiles;    // nb (nb + 1) / 2 upper-triangular tile pairs
   int tchunks;       // ceil(T / COLSTAT_ROWS)
-  int win_rows;      // rows per window wave (R)
-  int win_splits;    // column splits per row block (W)
-  int64_t win_units; // row blocks * splits
-  size_t win_lds;    // bytes of LDS per window wave
+  int win_splits;    // column splits (waves) per window row block (W)
   traknn::Layout lay;
   // timing
   int timing;
@@ -91,8 +83,7 @@ hipError_t launch_gram(const void* xc, const float* ncs, int64_t T, int64_t Tpad
                        float* S, int64_t ldS, hipStream_t s);
 // window_topk.hip
 hipError_t launch_window_topk(const float* S, int64_t ldS, int64_t T, int L_min,
-                              int L_max, int k, int rows, int splits,
-                              int64_t units, size_t lds_bytes, double* part_d,
+                              int L_max, int k, int splits, double* part_d,
                               int32_t* part_i, hipStream_t s);
 hipError_t launch_merge(const double* part_d, const int32_t* part_i, int64_t T,
                         int L_min, int L_max, int k, int splits, int32_t* idx,
@@ -105,8 +96,8 @@ hipError_t launch_backward(const float* X, int64_t ldx, int64_t T, int64_t D,
                            float* g, int64_t ldg, int32_t* cnt, int32_t* ptr,
                            int32_t* fill, int32_t* rev, hipStream_t s);
 
-// Window stage sizing shared by the planner and the launcher.
-size_t window_lds_bytes(int L_max, int NL, int k, int rows);
+// Window stage sizing shared by the planner and the launcher: LDS bytes of a
+// workgroup of W waves for length L and k neighbours.
 size_t window1_lds_bytes(int L, int k, int W);
 #ifndef TRAKNN_WINDOW1_ROWS
 #define TRAKNN_WINDOW1_ROWS 16

@@ -8,26 +8,20 @@
 // row r = r0 + s, i.e. one coalesced 256-byte segment of S per step, and each
 // lane advances its own window with the recurrence
 //   D <- (D - d(r, r+delta)) + d(r+L, r+L+delta)             (Eq. 5)
-// in FP64. Every wave restarts its window with a direct L-term sum at the top
-// of each row block, so rounding can never drift over more than R steps (and
-// for FP32 inputs whose exponents span less than ~29 bits the FP64 recurrence
-// is exact).
+// in FP64. Every row block restarts its windows with a direct L-term sum, so
+// rounding can never drift over more than a block's rows (and for FP32 inputs
+// whose exponents span less than ~29 bits the FP64 recurrence is exact).
 //
 // The 64 candidates of a step all belong to the same row, so the top-k filter
-// is one compare per lane against that row's current k-th best key
-// (distance, index), broadcast from the lane that keeps the row's threshold,
-// and one ballot. Insertions are rare after the first few chunks; they are
-// done wave-cooperatively on the row's sorted list in LDS (lane q holds entry
-// q, a one-lane shift inserts a candidate).
+// is one compare per lane against that row's bound and one ballot; the rare
+// insertions shift a sorted list held one entry per lane.
 //
-// Multi-length sweeps (L = 1..Lmax in one pass) extend the window along the
-// diagonal instead: D_1 = d(r, c), D_L = D_{L-1} + d(r+L-1, c+L-1), each with its
-// own lists and its own exclusion |i - j| >= L.
-//
-// Work split: a wave owns R consecutive rows and one of W contiguous ranges of
-// 64-diagonal chunks, writing a partial sorted list per row; the merge kernel
-// combines the W partial lists of a row into the final k in (distance, index)
-// order. Everything is deterministic (no atomics).
+// A multi-length request (L = L_min .. L_max) runs the kernel once per length
+// on the same distance matrix, each with its own lists and exclusion zone
+// |i - j| >= L; the merge kernel then combines, per length and row, the W
+// partial lists of the row's column ranges into the final k in (distance,
+// index) order. The result does not depend on the order in which the waves
+// run.
 #include <cfloat>
 #include <climits>
 #include <type_traits>
@@ -48,173 +42,12 @@ __device__ __forceinline__ bool key_less(double ad, int ai, double bd, int bi) {
   return (ad < bd) | ((ad == bd) & (ai < bi));
 }
 
-template <int LMAX, bool SWEEP, int R>
-struct WinCfg {
-  static constexpr int NLT = SWEEP ? LMAX : 1;
-  static constexpr int M = R + LMAX - 1;  // S values a lane needs per chunk
-  static constexpr size_t vals_bytes = (size_t)M * 64 * sizeof(float);
-};
-
-// Insert the ballot mask's candidates into the list of row s (list li).
-__device__ __forceinline__ void insert_candidates(
-    uint64_t mask, double D, int col, int s, int k, double* ld, int* li_,
-    int base, int lane, double& thr_d, int& thr_i) {
-  double ed = lane < k ? ld[base + lane] : __builtin_huge_val();
-  int ei = lane < k ? li_[base + lane] : INT_MAX;
-  while (mask) {
-    const int src = __builtin_ctzll(mask);
-    mask &= mask - 1;
-    const double cd = readlane_d(D, src);
-    const int ci = __builtin_amdgcn_readlane(col, src);
-    const double kd = readlane_d(ed, k - 1);
-    const int ki = __builtin_amdgcn_readlane(ei, k - 1);
-    if (!key_less(cd, ci, kd, ki)) continue;
-    const double pd = __shfl_up(ed, 1, 64);
-    const int pi = __shfl_up(ei, 1, 64);
-    const bool lt_prev = lane > 0 && key_less(cd, ci, pd, pi);
-    const bool lt_self = key_less(cd, ci, ed, ei);
-    if (lt_prev) {
-      ed = pd;
-      ei = pi;
-    } else if (lt_self) {
-      ed = cd;
-      ei = ci;
-    }
-  }
-  if (lane < k) {
-    ld[base + lane] = ed;
-    li_[base + lane] = ei;
-  }
-  const double nd = readlane_d(ed, k - 1);
-  const int ni = __builtin_amdgcn_readlane(ei, k - 1);
-  // the row's new k-th key goes back to the lane that keeps its threshold
-  if (lane == s) {
-    thr_d = nd;
-    thr_i = ni;
-  }
-}
-
-template <int LMAX, bool SWEEP, int R>
-__global__ __launch_bounds__(64) void window_topk_kernel(
-    const float* __restrict__ S, int64_t ldS, int T, int np0, int k, int W,
-    double* __restrict__ part_d, int32_t* __restrict__ part_i) {
-  using C = WinCfg<LMAX, SWEEP, R>;
-  constexpr int NLT = C::NLT;
-  constexpr int M = C::M;
-  extern __shared__ __attribute__((aligned(16))) char smem[];
-  float* vl = (float*)smem;
-  double* ld = (double*)(smem + C::vals_bytes);
-  int* li_ = (int*)(ld + (size_t)NLT * R * k);
-
-  const int lane = threadIdx.x;
-  const int64_t unit = blockIdx.x;
-  const int rb = (int)(unit / W);
-  const int split = (int)(unit % W);
-  const int r0 = rb * R;
-
-  for (int q = lane; q < NLT * R * k; q += 64) {
-    ld[q] = __builtin_huge_val();
-    li_[q] = INT_MAX;
-  }
-  double thr_d[NLT];
-  int thr_i[NLT];
-#pragma unroll
-  for (int q = 0; q < NLT; ++q) {
-    thr_d[q] = __builtin_huge_val();
-    thr_i[q] = INT_MAX;
-  }
-
-  const int64_t dlo = -(int64_t)(r0 + R - 1);
-  const int64_t ND = (int64_t)np0 + R - 1;
-  const int64_t NC = (ND + 63) / 64;
-  const int64_t cb = (int64_t)split * NC / W, ce = (int64_t)(split + 1) * NC / W;
-
-  float nv[M];
-  auto gload = [&](int64_t c) {
-    const int64_t delta = dlo + 64 * c + lane;
-#pragma unroll
-    for (int m = 0; m < M; ++m) {
-      const int64_t row = r0 + m;
-      const int64_t col = row + delta;
-      nv[m] = (row < T && col >= 0 && col < T) ? S[row * ldS + col] : 0.f;
-    }
-  };
-  if (cb < ce) gload(cb);
-  for (int64_t c = cb; c < ce; ++c) {
-    __syncthreads();
-#pragma unroll
-    for (int m = 0; m < M; ++m) vl[m * 64 + lane] = nv[m];
-    __syncthreads();
-    if (c + 1 < ce) gload(c + 1);
-    const int64_t delta64 = dlo + 64 * c + lane;
-    const int delta = (int)delta64;
-    const int adelta = delta < 0 ? -delta : delta;
-
-    if constexpr (!SWEEP) {
-      constexpr int L = LMAX;
-      const int npL = T - L + 1;
-      double D = 0.0;
-#pragma unroll
-      for (int l = 0; l < L; ++l) D += (double)vl[l * 64 + lane];
-      for (int s = 0; s < R; ++s) {
-        const int r = r0 + s;
-        if (r >= npL) break;
-        const int col = r + delta;
-        const bool valid = adelta >= L && col >= 0 && col < npL;
-        const double td = readlane_d(thr_d[0], s);
-        const int ti = __builtin_amdgcn_readlane(thr_i[0], s);
-        const uint64_t mask = __ballot(valid & key_less(D, col, td, ti));
-        if (mask)
-          insert_candidates(mask, D, col, s, k, ld, li_, s * k, lane, thr_d[0], thr_i[0]);
-        if (s + 1 < R)
-          D = (D - (double)vl[s * 64 + lane]) + (double)vl[(s + L) * 64 + lane];
-      }
-    } else {
-      for (int s = 0; s < R; ++s) {
-        const int r = r0 + s;
-        if (r >= np0) break;
-        const int col = r + delta;
-        double D = 0.0;
-#pragma unroll
-        for (int L = 1; L <= LMAX; ++L) {
-          D += (double)vl[(s + L - 1) * 64 + lane];
-          const int npL = T - L + 1;
-          if (r < npL) {
-            const bool valid = adelta >= L && col >= 0 && col < npL;
-            const double td = readlane_d(thr_d[L - 1], s);
-            const int ti = __builtin_amdgcn_readlane(thr_i[L - 1], s);
-            const uint64_t mask = __ballot(valid & key_less(D, col, td, ti));
-            if (mask)
-              insert_candidates(mask, D, col, s, k, ld, li_, ((L - 1) * R + s) * k,
-                                lane, thr_d[L - 1], thr_i[L - 1]);
-          }
-        }
-      }
-    }
-  }
-  __syncthreads();
-  // partial lists: part[((split * NLT + li) * np0 + row) * k + q]
-  for (int q = lane; q < NLT * R * k; q += 64) {
-    const int li = q / (R * k);
-    const int s = (q / k) % R;
-    const int e = q % k;
-    const int row = r0 + s;
-    if (row < np0) {
-      const int64_t o = (((int64_t)split * NLT + li) * np0 + row) * k + e;
-      part_d[o] = ld[q];
-      part_i[o] = li_[q];
-    }
-  }
-}
-
 // ---------------------------------------------------------------------------
-// Single trajectory length, register-resident (the headline path).
+// Window + top-k kernel for one trajectory length L.
 //
-// Each lane keeps the R + L - 1 values of its diagonal for the current chunk
-// in registers (the next chunk's values are loaded meanwhile) and the R-step
-// recurrence is fully unrolled, so a step is: two FP64 adds, three readlanes
-// of the row's threshold, a few compares folded into one ballot, and a branch
-// that is almost never taken.
+// Each lane holds the R + L - 1 values of its diagonal for the current chunk
+// (the next chunk's values are loaded meanwhile); a step is two FP64 adds, two
+// readlanes of the row's bound, one compare and a ballot.
 //
 // The first chunk of a wave seeds each row's list with a wave-wide bitonic
 // sort of its 64 candidates (the lists start empty, so every candidate would
@@ -322,7 +155,7 @@ __device__ __forceinline__ void seed_row(double d, int c, bool valid, int k, dou
 // a few per row block) skip the per-lane validity tests.
 template <int L>
 __global__ __launch_bounds__(1024) void window1_kernel(
-    const float* __restrict__ S, int64_t ldS, int T, int k, int W,
+    const float* __restrict__ S, int64_t ldS, int T, int k, int W, int64_t split_stride,
     double* __restrict__ part_d, int32_t* __restrict__ part_i) {
   constexpr int R = W1_ROWS;
   constexpr int U = W1_GROUP;
@@ -474,25 +307,26 @@ __global__ __launch_bounds__(1024) void window1_kernel(
     else
       scan_chunk(c, std::true_type{});
   }
-  // partial lists: part[(split * npL + row) * k + q]; a range with no chunk
-  // leaves its lists empty
+  // partial lists: part[(split * split_stride + row) * k + q]; a range with no
+  // chunk leaves its lists empty
   for (int s = 0; s < nrows; ++s) {
     const int row = r0 + s;
     if (lane < k) {
-      const int64_t o = ((int64_t)split * npL + row) * k + lane;
+      const int64_t o = ((int64_t)split * split_stride + row) * k + lane;
       part_d[o] = cb < ce ? ld[s * k + lane] : __builtin_huge_val();
       part_i[o] = cb < ce ? li[s * k + lane] : INT_MAX;
     }
   }
 }
 
+// Row blocks of length L: ceil((T - L + 1) / W1_ROWS) workgroups of W waves.
 template <int L>
-hipError_t launch_win1(const float* S, int64_t ldS, int T, int k, int W, int64_t units,
+hipError_t launch_win1(const float* S, int64_t ldS, int T, int k, int W, int64_t split_stride,
                        double* pd, int32_t* pi, hipStream_t s) {
   const size_t lds = window1_lds_bytes(L, k, W);
-  const unsigned blocks = (unsigned)(units / W);
-  hipLaunchKernelGGL((window1_kernel<L>), dim3(blocks), dim3(64 * W), lds, s, S, ldS,
-                     T, k, W, pd, pi);
+  const unsigned blocks = (unsigned)((T - L + 1 + W1_ROWS - 1) / W1_ROWS);
+  hipLaunchKernelGGL((window1_kernel<L>), dim3(blocks), dim3(64 * W), lds, s, S, ldS, T,
+                     k, W, split_stride, pd, pi);
   return hipGetLastError();
 }
 
@@ -555,54 +389,6 @@ __global__ __launch_bounds__(256) void score_kernel(
   scores[g] = s / (double)k;
 }
 
-template <int LMAX, bool SWEEP, int R>
-hipError_t launch_win(const float* S, int64_t ldS, int T, int np0, int k, int W,
-                      int64_t units, size_t lds, double* pd, int32_t* pi,
-                      hipStream_t s) {
-  hipLaunchKernelGGL((window_topk_kernel<LMAX, SWEEP, R>), dim3((unsigned)units),
-                     dim3(64), lds, s, S, ldS, T, np0, k, W, pd, pi);
-  return hipGetLastError();
-}
-
-template <int LMAX, bool SWEEP>
-hipError_t launch_win_r(int rows, const float* S, int64_t ldS, int T, int np0,
-                        int k, int W, int64_t units, size_t lds, double* pd,
-                        int32_t* pi, hipStream_t s) {
-  if (rows == 32)
-    return launch_win<LMAX, SWEEP, 32>(S, ldS, T, np0, k, W, units, lds, pd, pi, s);
-  return launch_win<LMAX, SWEEP, 4>(S, ldS, T, np0, k, W, units, lds, pd, pi, s);
-}
-
-template <bool SWEEP>
-hipError_t launch_win_l(int L, int rows, const float* S, int64_t ldS, int T,
-                        int np0, int k, int W, int64_t units, size_t lds,
-                        double* pd, int32_t* pi, hipStream_t s) {
-  switch (L) {
-#define TRAKNN_WIN_CASE(n) \
-  case n:                  \
-    return launch_win_r<n, SWEEP>(rows, S, ldS, T, np0, k, W, units, lds, pd, pi, s);
-    TRAKNN_WIN_CASE(1)
-    TRAKNN_WIN_CASE(2)
-    TRAKNN_WIN_CASE(3)
-    TRAKNN_WIN_CASE(4)
-    TRAKNN_WIN_CASE(5)
-    TRAKNN_WIN_CASE(6)
-    TRAKNN_WIN_CASE(7)
-    TRAKNN_WIN_CASE(8)
-    TRAKNN_WIN_CASE(9)
-    TRAKNN_WIN_CASE(10)
-    TRAKNN_WIN_CASE(11)
-    TRAKNN_WIN_CASE(12)
-    TRAKNN_WIN_CASE(13)
-    TRAKNN_WIN_CASE(14)
-    TRAKNN_WIN_CASE(15)
-    TRAKNN_WIN_CASE(16)
-#undef TRAKNN_WIN_CASE
-    default:
-      return hipErrorInvalidValue;
-  }
-}
-
 }  // namespace
 
 size_t window1_lds_bytes(int L, int k, int W) {
@@ -610,20 +396,23 @@ size_t window1_lds_bytes(int L, int k, int W) {
          (size_t)W * (W1_VALS_BYTES(W1_ROWS + L - 1 + W1_GROUP) + (size_t)W1_ROWS * k * 12);
 }
 
-size_t window_lds_bytes(int L_max, int NL, int k, int rows) {
-  return (size_t)(rows + L_max - 1) * 64 * sizeof(float) + (size_t)NL * rows * k * 12;
-}
-
 hipError_t launch_window_topk(const float* S, int64_t ldS, int64_t T, int L_min,
-                              int L_max, int k, int rows, int splits,
-                              int64_t units, size_t lds_bytes, double* part_d,
+                              int L_max, int k, int splits, double* part_d,
                               int32_t* part_i, hipStream_t s) {
-  const int np0 = (int)(T - L_min + 1);
-  if (L_min == L_max) {
-    switch (L_max) {
+  const int64_t np0 = T - L_min + 1;
+  const int NL = L_max - L_min + 1;
+  // partial lists: [split][length][row][k]
+  const int64_t split_stride = (int64_t)NL * np0;
+  for (int L = L_min; L <= L_max; ++L) {
+    const int64_t off = (int64_t)(L - L_min) * np0 * k;
+    double* pd = part_d + off;
+    int32_t* pi = part_i + off;
+    hipError_t e;
+    switch (L) {
 #define TRAKNN_WIN1_CASE(n) \
   case n:                   \
-    return launch_win1<n>(S, ldS, (int)T, k, splits, units, part_d, part_i, s);
+    e = launch_win1<n>(S, ldS, (int)T, k, splits, split_stride, pd, pi, s); \
+    break;
       TRAKNN_WIN1_CASE(1)
       TRAKNN_WIN1_CASE(2)
       TRAKNN_WIN1_CASE(3)
@@ -644,10 +433,9 @@ hipError_t launch_window_topk(const float* S, int64_t ldS, int64_t T, int L_min,
       default:
         return hipErrorInvalidValue;
     }
+    if (e != hipSuccess) return e;
   }
-  if (L_min != 1) return hipErrorInvalidValue;
-  return launch_win_l<true>(L_max, rows, S, ldS, (int)T, np0, k, splits, units,
-                            lds_bytes, part_d, part_i, s);
+  return hipSuccess;
 }
 
 hipError_t launch_merge(const double* part_d, const int32_t* part_i, int64_t T,
