@@ -9,7 +9,8 @@
 // per-bucket sort by t, so the reverse lists -- and hence every floating-point
 // sum -- come out in the same order on every run. Each output row is then
 // gathered by one workgroup in FP64 (field differences of FP32 inputs are
-// exact in FP64) and rounded once to FP32. No distance value is needed: the
+// exact in FP64) and rounded once to FP32; rows that no term touches keep the
+// zeros of a fill pass and are not gathered. No distance value is needed: the
 // derivative of a squared distance is the field difference itself.
 #include "internal.h"
 
@@ -90,7 +91,30 @@ __global__ __launch_bounds__(256) void rev_sort_kernel(const int32_t* __restrict
   }
 }
 
-constexpr int GCOLS = 8;  // columns per thread per pass
+constexpr int GCOLS = 32;  // columns per thread per pass (8192 per pass)
+
+// Does output row a receive any term? (Rows that do not keep the zeros the
+// fill kernel wrote.)
+__device__ __forceinline__ bool row_has_terms(int a, int np, int L, const double* w,
+                                              const int32_t* ptr) {
+  for (int m = 0; m < L; ++m) {
+    const int t = a - m;
+    if (t >= 0 && t < np && (w[t] != 0.0 || ptr[t + 1] > ptr[t])) return true;
+  }
+  return false;
+}
+
+// Zero every row of the gradient: block b clears 1024 floats of row
+// b / per_row.
+__global__ __launch_bounds__(256) void zero_rows_kernel(float* __restrict__ g, int64_t ldg,
+                                                        int64_t D, int64_t per_row) {
+  const int64_t row = blockIdx.x / per_row;
+  const int64_t p0 = (blockIdx.x % per_row) * 1024 + threadIdx.x;
+  float* r = g + row * ldg;
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+    if (p0 + 256 * u < D) r[p0 + 256 * u] = 0.f;
+}
 
 __global__ __launch_bounds__(256) void grad_rows_kernel(
     const float* __restrict__ X, int64_t ldx, int T, int64_t D, int L, int k,
@@ -99,6 +123,7 @@ __global__ __launch_bounds__(256) void grad_rows_kernel(
     float* __restrict__ g, int64_t ldg) {
   const int a = blockIdx.x;
   const int np = T - L + 1;
+  if (!row_has_terms(a, np, L, w, ptr)) return;  // stays zero
   const double invk = 1.0 / (double)k;
   const float* xa = X + (int64_t)a * ldx;
   for (int64_t c0 = 0; c0 < D; c0 += 256 * GCOLS) {
@@ -169,6 +194,9 @@ hipError_t launch_backward(const float* X, int64_t ldx, int64_t T, int64_t D,
   hipLaunchKernelGGL(rev_fill_kernel, dim3(gk), dim3(256), 0, s, idx, w, np, k, ptr,
                      fill, rev);
   hipLaunchKernelGGL(rev_sort_kernel, dim3(gb), dim3(256), 0, s, ptr, np, rev);
+  const int64_t per_row = (D + 1023) / 1024;
+  hipLaunchKernelGGL(zero_rows_kernel, dim3((unsigned)(T * per_row)), dim3(256), 0, s, g, ldg,
+                     D, per_row);
   hipLaunchKernelGGL(grad_rows_kernel, dim3((unsigned)T), dim3(256), 0, s, X, ldx,
                      (int)T, D, L, k, idx, w, ptr, rev, g, ldg);
   return hipGetLastError();
