@@ -49,8 +49,8 @@ constexpr int BM = WT_M / 32, BN = WT_N / 32;  // MFMA blocks per wave
 static_assert(WT_M == 128, "the epilogue parks 32-row bands of 128-row wave tiles");
 // s_waitcnt immediate waiting for vmcnt == 0 only (expcnt, lgkmcnt at max)
 constexpr int VMCNT0 = 0x0F70;
-// vmcnt <= 8 (expcnt, lgkmcnt at max)
-constexpr int VMCNT_LE8 = 0x0F78;
+// s_waitcnt immediate for vmcnt <= n (expcnt, lgkmcnt at max)
+constexpr int vmcnt_le(int n) { return (n & 15) | (7 << 4) | (15 << 8) | ((n >> 4) << 14); }
 constexpr int EPI_PITCH = 36;  // floats per parked accumulator column (32 + 4)
 static_assert((GRAM_THREADS / 64) * (TILE / (GRAM_THREADS / 64 / 2)) * EPI_PITCH * 4 <=
                   GRAM_STAGES * 2 * TILE * RB,
@@ -322,7 +322,8 @@ __global__ __launch_bounds__(GRAM_THREADS, 1) void gram_kernel(
   issue_stage(0);
   if (nstages > 1) {
     issue_stage(1);
-    __builtin_amdgcn_s_waitcnt(VMCNT_LE8);  // stage 0 has landed
+    // stage 0 has landed (stage 1's loads may still be in flight)
+    __builtin_amdgcn_s_waitcnt(vmcnt_le(2 * BLK_PER_WAVE));
   } else {
     __builtin_amdgcn_s_waitcnt(VMCNT0);
   }
