@@ -140,6 +140,45 @@ def test_multi_length_sweep():
         np.testing.assert_allclose(s[L - 1, :n], s1[0], rtol=1e-12)
 
 
+def test_sweep_all_lengths_max_k():
+    """L = 1..16 in one call with k = 64 (the largest lengths and list size)."""
+    T, D, Lmax, k = 400, 40, 16, 64
+    _say(f"[gpu] sweep L=1..{Lmax} k={k} T={T} D={D}")
+    Xn, _ = synth.make_fields(T, 5, 8, sigma=1.5, n_events=2, event_len=6, seed=21)
+    idx, dist, s = _run(Xn, 1, k, "bf16x3", L_max=Lmax)
+    S = oracle.snapshot_dist(Xn)
+    for L in range(1, Lmax + 1):
+        n = T - L + 1
+        Dm = oracle.traj_dist_from_snapshot(S, L)
+        ref = oracle.knn_from_rows(Dm, np.arange(n), L, k)
+        stats = check_rows(Xn, L, k, np.arange(n), idx[L - 1, :n], dist[L - 1, :n],
+                           s[L - 1, :n], 1e-5, ref=ref + (Dm,),
+                           norm_tol=gram_norm_tol("bf16x3", D))
+        if L in (1, 8, 16):
+            _say(f"  L={L}: {stats}")
+        assert np.all(idx[L - 1, n:] == -1) and np.all(np.isnan(s[L - 1, n:]))
+
+
+def test_strided_and_unaligned_inputs():
+    """Rows with a stride beyond D (a view into wider rows) and a D that is not a
+    multiple of 4 give exactly the results of a contiguous copy."""
+    tk = _tk()
+    for D, extra in ((96, 12), (77, 0)):
+        _say(f"[gpu] strided input D={D} row padding {extra}")
+        Xn, _ = synth.make_fields(300, 1, D, sigma=2.0, n_events=1, event_len=3, seed=D)
+        wide = np.zeros((300, D + extra + (4 - (D + extra) % 4) % 4), dtype=np.float32)
+        wide[:, :D] = Xn
+        Xw = torch.from_numpy(wide).cuda()[:, :D]
+        Xc = torch.from_numpy(np.ascontiguousarray(Xn)).cuda()
+        for prec in ("bf16x3", "fp32"):
+            p = tk.Plan(300, D, 3, 3, 6, prec)
+            i1, d1 = p.knn(Xw)
+            i2, d2 = p.knn(Xc)
+            torch.cuda.synchronize()
+            assert torch.equal(i1, i2) and torch.equal(d1, d2)
+            p.close()
+
+
 def test_determinism():
     w = synth.WORKLOADS["tiny"]
     _say("[gpu] determinism")
