@@ -161,8 +161,9 @@ def main():
                     help="also run a plain device copy of this many GiB (counter scale)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU: this build has no multi-GPU path "
-              "(see DESIGN.md for how the hot path would shard).", file=sys.stderr)
+        print("bench.py runs on one GPU: the library has no multi-GPU path "
+              "(the tile pairs would shard across GPUs with one exchange of partial "
+              "neighbour lists).", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -47,7 +47,7 @@ extern "C" {
 /* Status codes. */
 #define TRAKNN_OK 0
 #define TRAKNN_ERR_INVALID_ARG (-1) /* a size, pointer, stride or alignment is invalid */
-#define TRAKNN_ERR_UNSUPPORTED (-2) /* valid request outside what this build implements */
+#define TRAKNN_ERR_UNSUPPORTED (-2) /* valid request outside what this library implements */
 #define TRAKNN_ERR_WORKSPACE (-3)   /* workspace pointer NULL/misaligned or too small */
 #define TRAKNN_ERR_HIP (-4)         /* a HIP runtime call or kernel launch failed */
 
