@@ -140,6 +140,18 @@ int traknn_knn(traknn_plan_t plan, const float* X, int64_t ldx, void* workspace,
 int traknn_score(traknn_plan_t plan, const double* nbr_dist, double* scores,
                  void* stream);
 
+/* Rarity scores for every neighbour count k' = 1..k from one search (paper,
+ * Eq. 3 and the discussion of reusing one k-NN pass for several k; k' = 1 is
+ * the trajectory analogue of the matrix profile). The lists of traknn_knn are
+ * sorted by (distance, index), so the k' nearest are their first k' entries:
+ *   scores[l][t][q] = (1/(q+1)) * sum_{r<=q} nbr_dist[l][t][r]
+ * summed in rank order in FP64; scores[l][t][k-1] equals traknn_score's s.
+ *   nbr_dist [in]  as written by traknn_knn for the same plan.
+ *   scores   [out] FP64 [L_max-L_min+1][T-L_min+1][k]; NaN in non-existent rows.
+ * Errors: INVALID_ARG, HIP. */
+int traknn_score_prefix(traknn_plan_t plan, const double* nbr_dist, double* scores,
+                        void* stream);
+
 /* Gradient of F = sum_t grad_scores[t] * s_t with respect to X, the neighbour
  * sets held fixed (differentiating Eq. 2 inside Eq. 3):
  *   dF/dx_a = (2/k) sum_t w_t sum_{j in N_t} sum_{m<L}

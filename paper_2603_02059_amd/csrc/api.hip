@@ -260,6 +260,14 @@ int traknn_score(traknn_plan_t plan, const double* nbr_dist, double* scores,
                                (hipStream_t)stream));
 }
 
+int traknn_score_prefix(traknn_plan_t plan, const double* nbr_dist, double* scores,
+                        void* stream) {
+  if (!plan || !nbr_dist || !scores) return TRAKNN_ERR_INVALID_ARG;
+  const traknn_config& c = plan->cfg;
+  return fail_hip(launch_score_prefix(nbr_dist, plan->T, c.L_min, c.L_max, c.k, scores,
+                                      (hipStream_t)stream));
+}
+
 int traknn_score_backward(traknn_plan_t plan, const float* X, int64_t ldx,
                           const int32_t* nbr_idx, const double* grad_scores,
                           float* grad_X, int64_t ldg, void* workspace,

@@ -54,7 +54,7 @@ __device__ __forceinline__ bool key_less(double ad, int ai, double bd, int bi) {
 // otherwise be inserted one by one). Later insertions shift the list one lane
 // with DPP wave_shr:1, a VALU move, instead of an LDS permute.
 // ---------------------------------------------------------------------------
-constexpr int W1_ROWS = WINDOW1_ROWS;  // rows per wave
+constexpr int W1_ROWS = WINDOW1_ROWS;  // rows per block
 constexpr int W1_GROUP = 8;   // steps unrolled per group
 #define W1_VALS_BYTES(M) (((size_t)(M) * 64 * sizeof(float) + 15) / 16 * 16)
 
@@ -389,6 +389,24 @@ __global__ __launch_bounds__(256) void score_kernel(
   scores[g] = s / (double)k;
 }
 
+// Scores for every k' <= k from one neighbour list (the lists are sorted by
+// (distance, index), so the k' nearest are its first k' entries): out[q] =
+// mean of dist[0..q], summed in rank order -- out[k-1] is exactly s_t.
+__global__ __launch_bounds__(256) void score_prefix_kernel(
+    const double* __restrict__ dist, int T, int np0, int Lmin, int NL, int k,
+    double* __restrict__ out) {
+  const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (g >= (int64_t)NL * np0) return;
+  const int li = (int)(g / np0);
+  const int t = (int)(g % np0);
+  const int npL = T - (Lmin + li) + 1;
+  double s = 0.0;
+  for (int q = 0; q < k; ++q) {
+    s += dist[g * k + q];
+    out[g * k + q] = t < npL ? s / (double)(q + 1) : __builtin_nan("");
+  }
+}
+
 }  // namespace
 
 size_t window1_lds_bytes(int L, int k, int W) {
@@ -457,6 +475,16 @@ hipError_t launch_score(const double* dist, int64_t T, int L_min, int L_max,
   const int64_t n = (int64_t)NL * np0;
   hipLaunchKernelGGL(score_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256),
                      0, s, dist, (int)T, np0, L_min, NL, k, scores);
+  return hipGetLastError();
+}
+
+hipError_t launch_score_prefix(const double* dist, int64_t T, int L_min, int L_max,
+                               int k, double* out, hipStream_t s) {
+  const int np0 = (int)(T - L_min + 1);
+  const int NL = L_max - L_min + 1;
+  const int64_t n = (int64_t)NL * np0;
+  hipLaunchKernelGGL(score_prefix_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256),
+                     0, s, dist, (int)T, np0, L_min, NL, k, out);
   return hipGetLastError();
 }
 

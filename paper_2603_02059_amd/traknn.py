@@ -35,7 +35,7 @@ MAX_K = 64
 STAGES = ("centre_stats", "centre_convert", "gram", "window_topk", "merge")
 
 EXPORTS = ("traknn_plan", "traknn_plan_destroy", "traknn_knn", "traknn_score",
-           "traknn_score_backward", "traknn_status_string", "traknn_set_timing",
+           "traknn_score_prefix", "traknn_score_backward", "traknn_status_string", "traknn_set_timing",
            "traknn_stage_times")
 
 
@@ -65,6 +65,7 @@ def _load() -> ctypes.CDLL:
     lib.traknn_plan_destroy.argtypes = [vp]
     lib.traknn_knn.argtypes = [vp, vp, i64, vp, sz, vp, vp, vp]
     lib.traknn_score.argtypes = [vp, vp, vp, vp]
+    lib.traknn_score_prefix.argtypes = [vp, vp, vp, vp]
     lib.traknn_score_backward.argtypes = [vp, vp, i64, vp, vp, vp, i64, vp, sz, vp]
     lib.traknn_status_string.argtypes = [i32]
     lib.traknn_status_string.restype = ctypes.c_char_p
@@ -129,6 +130,11 @@ def traknn_knn(plan, X, ldx: int, ws, ws_bytes: int, nbr_idx, nbr_dist,
 def traknn_score(plan, nbr_dist, scores, stream=None) -> None:
     _ck(_lib.traknn_score(plan, _ptr(nbr_dist), _ptr(scores), _stream(stream)),
         "traknn_score")
+
+
+def traknn_score_prefix(plan, nbr_dist, scores, stream=None) -> None:
+    _ck(_lib.traknn_score_prefix(plan, _ptr(nbr_dist), _ptr(scores), _stream(stream)),
+        "traknn_score_prefix")
 
 
 def traknn_score_backward(plan, X, ldx: int, nbr_idx, grad_scores, grad_X,
@@ -217,6 +223,14 @@ class Plan:
         if scores is None:
             scores = torch.empty((self.NL, self.np0), dtype=torch.float64, device=self.device)
         traknn_score(self.handle, dist, scores, stream)
+        return scores
+
+    def score_prefix(self, dist: torch.Tensor, scores=None, stream=None):
+        """Scores for every k' = 1..k: [NL, n', k] float64 (last column = score)."""
+        if scores is None:
+            scores = torch.empty((self.NL, self.np0, self.k), dtype=torch.float64,
+                                 device=self.device)
+        traknn_score_prefix(self.handle, dist, scores, stream)
         return scores
 
     def backward(self, X: torch.Tensor, idx: torch.Tensor, grad_scores: torch.Tensor,

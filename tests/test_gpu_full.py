@@ -6,6 +6,7 @@ properties that hold for every row at any size.
     Gram precisions;
   * split: T = 27394, 128 x 256 (D = 32768), BF16x3 against FP16 and FP32;
   * all lengths: L = 1..10 in one sweep at T = 27394, D = 8192;
+  * small grid: T = 27394, 4 x 8 (D = 32), where the top-k stage dominates;
   * backward: T = 10957, D = 8192, L = 5, k = 10, the summed score of the 100
     rarest trajectories, against the oracle's analytic gradient and FP64
     central differences (h = 1e-3 Pa) on 64 cells.
@@ -15,7 +16,7 @@ import pytest
 
 import oracle
 from paper_2603_02059_amd import synth
-from tests.parity import check_rows, precision_tol
+from tests.parity import check_rows, gram_norm_tol, precision_tol
 
 pytestmark = pytest.mark.gpu
 
@@ -127,6 +128,21 @@ def test_all_lengths_sweep():
     # the sweep and a single-length run agree (same S, different summation order)
     i5, d5, s5 = _run(Xn, 5, 5, w.k, "bf16x3")
     np.testing.assert_allclose(s[4, : w.T - 4], s5[0], rtol=1e-12)
+
+
+def test_small_grid_full_length():
+    """A small-D shape (4 x 8 grid, D = 32, as after a PCA reduction) at the full
+    length: the Gram is tiny and the window/top-k stage dominates."""
+    T, L, k = 27394, 5, 10
+    _say(f"[gpu-full] small grid T={T} D=32 L={L} k={k}")
+    Xn, starts = synth.make_fields(T, 4, 8, sigma=1.0, n_events=20, event_len=5, seed=4)
+    idx, dist, s = _run(Xn, L, L, k, "bf16x3")
+    idx, dist, s = idx[0], dist[0], s[0]
+    _check_all_rows(idx, dist, s, L, k)
+    rows = _sample(idx.shape[0], starts, s, 48, L)
+    stats = check_rows(Xn, L, k, rows, idx[rows], dist[rows], s[rows],
+                       precision_tol("bf16x3"), norm_tol=gram_norm_tol("bf16x3", 32))
+    _say(f"  {stats}")
 
 
 def test_backward_config():

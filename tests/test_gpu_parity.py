@@ -179,6 +179,28 @@ def test_strided_and_unaligned_inputs():
             p.close()
 
 
+def test_prefix_scores_every_k():
+    """Scores for every k' <= k from one search equal separate searches with
+    k' neighbours; the last column is the score itself."""
+    tk = _tk()
+    w = synth.WORKLOADS["tiny"]
+    _say("[gpu] prefix scores k'=1..k")
+    Xn, _ = synth.make_workload(w)
+    X = torch.from_numpy(Xn).cuda()
+    k = 8
+    p = tk.Plan(w.T, w.D, w.L, w.L, k, "bf16x3")
+    idx, dist = p.knn(X)
+    sp = p.score_prefix(dist)
+    s = p.score(dist)
+    torch.cuda.synchronize()
+    sp, s = sp.cpu().numpy(), s.cpu().numpy()
+    p.close()
+    assert np.array_equal(sp[0, :, k - 1], s[0])
+    for kk in range(1, k + 1):
+        ref = oracle.knn(Xn, w.L, kk)[2]
+        np.testing.assert_allclose(sp[0, :, kk - 1], ref, rtol=1e-5)
+
+
 def test_determinism():
     w = synth.WORKLOADS["tiny"]
     _say("[gpu] determinism")
