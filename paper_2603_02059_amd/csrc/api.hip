@@ -17,7 +17,7 @@ constexpr int64_t MAX_T = 1 << 20;       // int32 indices with headroom
 constexpr int64_t MAX_D = (int64_t)1 << 28;
 constexpr size_t MAX_WIN_LDS = 64 * 1024;
 #ifndef TRAKNN_WIN_TARGET_UNITS
-#define TRAKNN_WIN_TARGET_UNITS 6144
+#define TRAKNN_WIN_TARGET_UNITS 12288
 #endif
 constexpr int64_t WIN_TARGET_UNITS = TRAKNN_WIN_TARGET_UNITS;
 constexpr int MAX_SPLITS = 16;

@@ -102,7 +102,7 @@ hipError_t launch_backward(const float* X, int64_t ldx, int64_t T, int64_t D,
 // workgroup of W waves for length L and k neighbours.
 size_t window1_lds_bytes(int L, int k, int W);
 #ifndef TRAKNN_WINDOW1_ROWS
-#define TRAKNN_WINDOW1_ROWS 16
+#define TRAKNN_WINDOW1_ROWS 8
 #endif
 constexpr int WINDOW1_ROWS = TRAKNN_WINDOW1_ROWS;  // rows per single-length window wave
 
