@@ -67,7 +67,7 @@ def gram_flops(T: int, D: int, prec: str) -> float:
     return passes * 2.0 * D * T * (T + 1) / 2.0
 
 
-def window_bytes(T: int, L: int, rows: int = 16) -> dict:
+def window_bytes(T: int, L: int, rows: int = 8) -> dict:
     """Bytes of S the window/top-k stage must read: the algorithmic figure is
     the upper triangle once (4 T(T+1)/2 B); this design reads every row of S
     (both triangles, so each row's candidates are contiguous) plus the L - 1
