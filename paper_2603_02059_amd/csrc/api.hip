@@ -16,6 +16,9 @@ constexpr size_t WS_ALIGN = 256;
 constexpr int64_t MAX_T = 1 << 20;       // int32 indices with headroom
 constexpr int64_t MAX_D = (int64_t)1 << 28;
 constexpr size_t MAX_WIN_LDS = 64 * 1024;
+// Window waves to aim for (row blocks x waves per block); a compile-time
+// tuning knob. 12288 gives 4 waves per 8-row block at T = 27394, the best of
+// the block shapes measured there.
 #ifndef TRAKNN_WIN_TARGET_UNITS
 #define TRAKNN_WIN_TARGET_UNITS 12288
 #endif

@@ -101,9 +101,11 @@ hipError_t launch_backward(const float* X, int64_t ldx, int64_t T, int64_t D,
 // Window stage sizing shared by the planner and the launcher: LDS bytes of a
 // workgroup of W waves for length L and k neighbours.
 size_t window1_lds_bytes(int L, int k, int W);
+// Rows per window block (a multiple of the 8-step group; compile-time tuning
+// knob, 8 measured best on the full workload).
 #ifndef TRAKNN_WINDOW1_ROWS
 #define TRAKNN_WINDOW1_ROWS 8
 #endif
-constexpr int WINDOW1_ROWS = TRAKNN_WINDOW1_ROWS;  // rows per single-length window wave
+constexpr int WINDOW1_ROWS = TRAKNN_WINDOW1_ROWS;
 
 }  // namespace traknn
