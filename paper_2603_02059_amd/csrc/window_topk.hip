@@ -56,6 +56,8 @@ __device__ __forceinline__ bool key_less(double ad, int ai, double bd, int bi) {
 // ---------------------------------------------------------------------------
 constexpr int W1_ROWS = WINDOW1_ROWS;  // rows per block
 constexpr int W1_GROUP = 8;   // steps unrolled per group
+static_assert(W1_ROWS % W1_GROUP == 0 && (W1_ROWS & (W1_ROWS - 1)) == 0 && W1_ROWS <= 64,
+              "rows per block: a power of two, a multiple of the group, at most a wave");
 #define W1_VALS_BYTES(M) (((size_t)(M) * 64 * sizeof(float) + 15) / 16 * 16)
 
 __device__ __forceinline__ double dpp_shr1_d(double v, double old) {
