@@ -76,8 +76,8 @@ def window_bytes(T: int, L: int, rows: int = 8) -> dict:
             "design_bytes": 4.0 * T * T * (rows + L - 1) / rows}
 
 
-def time_path(tk, torch, X, w, prec, steps, warmup):
-    p = tk.Plan(w.T, w.D, w.L, w.L, w.k, prec)
+def time_path(tk, torch, X, w, prec, steps, warmup, row_batch=0):
+    p = tk.Plan(w.T, w.D, w.L, w.L, w.k, prec, row_batch=row_batch)
     idx, dist = p.empty_outputs()
     scores = torch.empty((1, p.np0), dtype=torch.float64, device=X.device)
     for _ in range(warmup):
@@ -102,6 +102,7 @@ def time_path(tk, torch, X, w, prec, steps, warmup):
         "idx": idx[0],
         "dist": dist[0],
         "scores": scores[0],
+        "ws_bytes": p.ws_bytes,
     }
     p.close()
     return out
@@ -157,6 +158,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0,
                     help="seconds of oracle time for the CPU baseline (0 = skip)")
     ap.add_argument("--only", default=None, help="time one precision only")
+    ap.add_argument("--band-rows", type=int, default=4088,
+                    help="also time band mode (row-batched streaming) with passes of "
+                         "this many rows, BF16x3 (0 = skip)")
     ap.add_argument("--calibrate-copy-gib", type=float, default=0.0,
                     help="also run a plain device copy of this many GiB (counter scale)")
     args = ap.parse_args()
@@ -204,6 +208,31 @@ def main():
             f"{r['pairs_per_s']:.3e} pairs/s, stages {r['stage_ms']}, "
             f"gram {r['gram_tflops']:.1f} TFLOP/s")
         results[prec] = r
+
+    band = None
+    if args.band_rows > 0 and not args.only:
+        log(f"[bench] timing bf16x3 band mode, passes of {args.band_rows} rows: "
+            f"{args.warmup} warmup + {args.compare_steps} steps")
+        r = time_path(tk, torch, X, w, "bf16x3", args.compare_steps, args.warmup,
+                      row_batch=args.band_rows)
+        # MFMA work of the band passes: every pass contracts ceil(rows / 256)
+        # block-rows of 256 fields against all T columns
+        rb, tiles = args.band_rows, 0
+        for t0 in range(0, n, rb):
+            srows = min(min(rb, n - t0) + w.L - 1, w.T - t0)
+            tiles += -(-srows // 256)
+        flops = 3 * 2.0 * w.D * (tiles * 256) * w.T
+        band = {"row_batch": rb, "ms_per_step": r["ms_per_step"],
+                "pairs_per_s": pairs / (r["ms_per_step"] * 1e-3),
+                "passes_ms": r["stage_ms"]["gram"],
+                "mfma_work_vs_whole_matrix": flops / gram_flops(w.T, w.D, "bf16x3"),
+                "workspace_GiB": r["ws_bytes"] / 2 ** 30,
+                "whole_matrix_workspace_GiB": results.get("bf16x3", r)["ws_bytes"] / 2 ** 30}
+        if "bf16x3" in results:
+            a = np.sort(r["idx"].cpu().numpy(), 1)
+            b = np.sort(results["bf16x3"]["idx"].cpu().numpy(), 1)
+            band["rows_with_whole_matrix_set"] = float(np.all(a == b, axis=1).mean())
+        log(f"[bench] band mode: {band}")
 
     head = results[precs[0]]
     hp = head["prec"]
@@ -260,6 +289,7 @@ def main():
                       "gram_fp32_equiv_tflops": r["gram_fp32_equiv_tflops"]}
                   for p, r in results.items()},
         "window_hbm": window_hbm,
+        "band_mode": band,
         "parity_sample": par,
         "planted_in_top40": f"{planted_found}/{len(starts)}",
     }

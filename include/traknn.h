@@ -80,8 +80,21 @@ extern "C" {
  *   k           neighbours per trajectory, 1 <= k <= TRAKNN_MAX_K; every length
  *               must leave each row k candidates: T - L_max + 1 >= k + 2 L_max - 1.
  *   precision   TRAKNN_FP32, TRAKNN_BF16X3 or TRAKNN_FP16.
- *   row_batch   must be 0 (the whole T x T distance matrix is held in the
- *               workspace; see traknn_plan's workspace size). */
+ *   row_batch   0: the whole T x T distance matrix is held in the workspace
+ *               (about 4 T^2 bytes) and only its upper-triangular tiles are
+ *               contracted. > 0, a multiple of 8: band mode (row-batched
+ *               streaming, for T whose matrix does not fit; the paper names
+ *               out-of-core computation as future work, Sec. 7): each pass
+ *               computes the rows t0 .. t0 + row_batch + L_max - 2 of the
+ *               matrix against all T columns and emits the lists of
+ *               trajectories t0 .. t0 + row_batch - 1, so the workspace holds
+ *               (row_batch + L_max - 1) rows of it. A band cannot reuse the
+ *               mirrored half, so the Gram work is about twice that of the
+ *               whole-matrix mode, plus the part of each pass's last 256-row
+ *               block-row beyond its rows (none when row_batch + L_max - 1 is a
+ *               multiple of 256). Results agree with the whole-matrix mode
+ *               within the precision's rounding (different summation order of
+ *               the mirrored entries). */
 typedef struct {
   int64_t T;
   int64_t D;
@@ -103,8 +116,9 @@ typedef struct traknn_plan_s* traknn_plan_t;
  *                          threads when timing is enabled.
  *   workspace_bytes  [out] device bytes the caller must provide to traknn_knn
  *                          and traknn_score_backward (one size covers both).
- * Errors: INVALID_ARG for NULL pointers or sizes out of range; UNSUPPORTED for
- * row_batch != 0, a multi-length sweep with L_min != 1, or a D whose 256-field
+ * Errors: INVALID_ARG for NULL pointers, sizes out of range or a row_batch that
+ * is negative or not a multiple of 8; UNSUPPORTED for a multi-length sweep with
+ * L_min != 1, or a D whose 256-field
  * Gram operand panel would reach 2 GiB (D >= 2^21 for FP32 and BF16X3,
  * D >= 2^22 for FP16). */
 int traknn_plan(const traknn_config* cfg, traknn_plan_t* out,

@@ -36,11 +36,13 @@ int fail_hip(hipError_t e) { return e == hipSuccess ? TRAKNN_OK : TRAKNN_ERR_HIP
 // WINDOW1_ROWS rows (the waves split the block's diagonals and share a per-row
 // bound), with W as large as the LDS budget and the target parallelism allow.
 // A multi-length request runs the same kernel once per length; L_max sizes
-// the LDS and the rows of the shortest length size the grid.
+// the LDS and the rows of the shortest length (of one pass in band mode) size
+// the grid.
 bool plan_window(traknn_plan_s* p) {
   const int k = p->cfg.k;
   const int L = p->cfg.L_max;
-  const int64_t nrb = (p->np0 + WINDOW1_ROWS - 1) / WINDOW1_ROWS;
+  const int64_t rows = p->rb ? (p->rb < p->np0 ? p->rb : p->np0) : p->np0;
+  const int64_t nrb = (rows + WINDOW1_ROWS - 1) / WINDOW1_ROWS;
   const int64_t nchunks = (p->np0 + WINDOW1_ROWS - 1 + 63) / 64;
   const size_t base = window1_lds_bytes(L, k, 0);
   const size_t per_wave = window1_lds_bytes(L, k, 1) - base;
@@ -68,8 +70,9 @@ void plan_layout(traknn_plan_s* p) {
   L.mu = take((size_t)p->D * sizeof(double));
   L.ncs = take((size_t)norm_chunks(p->Dpad) * p->Tpad * sizeof(float));
   L.xc = take((size_t)p->Tpad * p->Dpad * elem_bytes(prec));
-  L.S = take((size_t)p->T * p->ldS * sizeof(float));
-  const size_t nparts = (size_t)p->win_splits * p->NL * p->np0 * p->cfg.k;
+  L.S = take((size_t)(p->rb ? p->band_rows : p->T) * p->ldS * sizeof(float));
+  const int64_t prows = p->rb && p->rb < p->np0 ? p->rb : p->np0;  // rows of one pass
+  const size_t nparts = (size_t)p->win_splits * p->NL * prows * p->cfg.k;
   L.part_d = take(nparts * sizeof(double));
   L.part_i = take(nparts * sizeof(int32_t));
   const size_t np = (size_t)(p->T - p->cfg.L_min + 1);
@@ -139,7 +142,8 @@ int traknn_plan(const traknn_config* cfg, traknn_plan_t* out,
   // every row of every length needs k candidates outside its exclusion zone
   if (c.T - c.L_max + 1 < (int64_t)c.k + 2 * c.L_max - 1)
     return TRAKNN_ERR_INVALID_ARG;
-  if (c.row_batch != 0) return TRAKNN_ERR_UNSUPPORTED;
+  // band mode: passes start on multiples of 8 rows (16-byte aligned norm loads)
+  if (c.row_batch < 0 || c.row_batch % 8 != 0) return TRAKNN_ERR_INVALID_ARG;
   if (c.L_min != c.L_max && c.L_min != 1) return TRAKNN_ERR_UNSUPPORTED;
   // the Gram stage addresses a 256-field operand panel with 32-bit offsets
   if ((uint64_t)round_up(c.D, stage_k(c.precision)) * elem_bytes(c.precision) * GRAM_TILE >
@@ -152,12 +156,15 @@ int traknn_plan(const traknn_config* cfg, traknn_plan_t* out,
   p->T = c.T;
   p->D = c.D;
   p->Dpad = round_up(c.D, stage_k(c.precision));
-  p->Tpad = round_up(c.T, GRAM_TILE);
+  p->rb = c.row_batch;
+  // a band's last block-row may reach one tile past the last field
+  p->Tpad = round_up(c.T, GRAM_TILE) + (p->rb ? GRAM_TILE : 0);
   p->ldS = round_up(c.T, 64);
   p->np0 = c.T - c.L_min + 1;
   p->NL = c.L_max - c.L_min + 1;
-  p->nb = (int)(p->Tpad / GRAM_TILE);
+  p->nb = (int)((c.T + GRAM_TILE - 1) / GRAM_TILE);
   p->ntiles = (int64_t)p->nb * (p->nb + 1) / 2;
+  p->band_rows = p->rb + c.L_max - 1 < c.T ? p->rb + c.L_max - 1 : c.T;
   p->tchunks = (int)((c.T + COLSTAT_ROWS - 1) / COLSTAT_ROWS);
   if (!plan_window(p)) {
     delete p;
@@ -238,6 +245,32 @@ int traknn_knn(traknn_plan_t plan, const float* X, int64_t ldx, void* workspace,
                                            ncs, s))))
     return rc;
   if ((rc = record(plan, 2, s))) return rc;
+  if (plan->rb) {
+    // band mode (row-batched streaming): per pass, the rows of S that the
+    // pass's trajectories reach, then their windows and lists
+    for (int64_t t0 = 0; t0 < plan->np0; t0 += plan->rb) {
+      const int64_t nt = plan->rb < plan->np0 - t0 ? plan->rb : plan->np0 - t0;
+      const int64_t srows = nt + c.L_max - 1 < plan->T - t0 ? nt + c.L_max - 1 : plan->T - t0;
+      const int nbi = (int)((srows + GRAM_TILE - 1) / GRAM_TILE);
+      if ((rc = fail_hip(launch_gram_band(xc, ncs, plan->T, plan->Tpad, plan->Dpad, plan->nb,
+                                          (int64_t)nbi * plan->nb, c.precision, t0, nbi,
+                                          srows, S, plan->ldS, s))))
+        return rc;
+      if ((rc = fail_hip(launch_window_band(S, plan->ldS, plan->T, c.L_min, c.L_max, c.k,
+                                            plan->win_splits, t0, t0 + srows, t0, nt,
+                                            part_d, part_i, s))))
+        return rc;
+      if ((rc = fail_hip(launch_merge_band(part_d, part_i, plan->T, c.L_min, c.L_max, c.k,
+                                           plan->win_splits, t0, nt, nbr_idx, nbr_dist, s))))
+        return rc;
+    }
+    // the passes interleave the three stages: the Gram slot times them all
+    if ((rc = record(plan, 3, s))) return rc;
+    if ((rc = record(plan, 4, s))) return rc;
+    if ((rc = record(plan, 5, s))) return rc;
+    if (plan->timing) plan->timed_calls++;
+    return TRAKNN_OK;
+  }
   if ((rc = fail_hip(launch_gram(xc, ncs, plan->T, plan->Tpad, plan->Dpad, plan->nb,
                                  plan->ntiles, c.precision, S, plan->ldS, s))))
     return rc;

@@ -25,6 +25,12 @@
 // ids round-robin to the 8 XCDs, so each XCD is handed a contiguous run of a
 // grouped tile order (4 block-rows x successive block-columns). The ~32 tiles
 // an XCD runs at once then share 4 A panels and ~8 B panels in its L2.
+//
+// Band mode (row-batched streaming, for T whose T x T matrix does not fit):
+// the kernel fills a band of rows a_row0 .. a_row0 + rows_out - 1 against all
+// T columns, every tile (I, J) of the rectangle computed directly and stored
+// once, into a buffer whose row 0 is field a_row0. Symmetry cannot be used
+// there, since the mirrored rows belong to other bands.
 #include <type_traits>
 
 #include "internal.h"
@@ -96,6 +102,22 @@ __device__ __forceinline__ bool decode_tile(int64_t wg, int nb, int64_t ntiles,
     u -= cnt;
   }
   return false;
+}
+
+// Band mode: tile id -> (I, J) over nbi band block-rows x nb block-columns,
+// in the same grouped, XCD-aware order.
+__device__ __forceinline__ bool decode_rect(int64_t wg, int nbi, int nb, int64_t ntiles,
+                                            int& I, int& J) {
+  const int64_t per = (ntiles + NUM_XCD - 1) / NUM_XCD;
+  const int64_t lin = (wg % NUM_XCD) * per + wg / NUM_XCD;
+  if (lin >= ntiles) return false;
+  const int64_t grp = (int64_t)GRAM_GROUP_ROWS * nb;  // tiles of a full group
+  const int I0 = (int)(lin / grp) * GRAM_GROUP_ROWS;
+  const int64_t u = lin % grp;
+  const int gm = nbi - I0 < GRAM_GROUP_ROWS ? nbi - I0 : GRAM_GROUP_ROWS;
+  J = (int)(u / gm);
+  I = I0 + (int)(u % gm);
+  return true;
 }
 
 // Scheduling-group masks for __builtin_amdgcn_sched_group_barrier.
@@ -213,22 +235,29 @@ __device__ __forceinline__ void interleave_reads() {
   }
 }
 
-template <int PREC>
+template <int PREC, bool BAND>
 __global__ __launch_bounds__(GRAM_THREADS, 1) void gram_kernel(
     const char* __restrict__ xc, int64_t pitch, int nstages,
     const float* __restrict__ ncs, int64_t T, int64_t Tpad, int nb, int64_t ntiles,
-    float* __restrict__ S, int64_t ldS) {
+    int64_t a_row0, int nbi, int64_t rows_out, float* __restrict__ S, int64_t ldS) {
   __shared__ __attribute__((aligned(16))) char lds[GRAM_STAGES * 2 * OPER_BYTES + NORM_LDS];
   float* const nrm = (float*)(lds + GRAM_STAGES * 2 * OPER_BYTES);  // [2][I 256 | J 256]
   int I, J;
-  if (!decode_tile(blockIdx.x, nb, ntiles, I, J)) return;
+  if constexpr (BAND) {
+    if (!decode_rect(blockIdx.x, nbi, nb, ntiles, I, J)) return;
+  } else {
+    if (!decode_tile(blockIdx.x, nb, ntiles, I, J)) return;
+  }
+  // first fields of the tile's A and B panels
+  const int64_t arow = (BAND ? a_row0 : 0) + (int64_t)I * TILE;
+  const int64_t brow = (int64_t)J * TILE;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
   const int wm = w / WAVES_N, wn = w % WAVES_N;
-  const char* Ag = xc + (int64_t)I * TILE * pitch;
-  const char* Bg = xc + (int64_t)J * TILE * pitch;
+  const char* Ag = xc + arow * pitch;
+  const char* Bg = xc + brow * pitch;
 
   // Direct buffer -> LDS loads (buffer_load_dwordx4 ... lds): lane q of a load
   // lands at byte 16*q of the wave's 1 KB destination block, so each lane
@@ -274,7 +303,7 @@ __global__ __launch_bounds__(GRAM_THREADS, 1) void gram_kernel(
   // Chunk norms: wave 0 fetches the chunk's 256 N_i^c, wave 1 the 256 N_j^c
   // (one 1 KB direct load each) into the chunk's LDS slot.
   auto issue_norms = [&](int ch) {
-    const float* src = ncs + (int64_t)ch * Tpad + (int64_t)(w == 0 ? I : J) * TILE + 4 * lane;
+    const float* src = ncs + (int64_t)ch * Tpad + (w == 0 ? arow : brow) + 4 * lane;
     __builtin_amdgcn_global_load_lds(src, nrm + (ch & 1) * 2 * TILE + w * TILE, 16, 0, 0);
   };
   // acc += -(N_i^c + N_j^c)/2 as a depth-2 FP32 MFMA: lanes 0-31 supply
@@ -365,7 +394,7 @@ __global__ __launch_bounds__(GRAM_THREADS, 1) void gram_kernel(
   // the mirrored (j, i).
   constexpr int NWAVES = GRAM_THREADS / 64;
   float* stg = (float*)lds;  // [NWAVES][WT_N][EPI_PITCH]
-  const bool diag = I == J;
+  const bool diag = !BAND && I == J;
   const int64_t i_base = (int64_t)I * TILE, j_base = (int64_t)J * TILE;
 #pragma unroll
   for (int bm = 0; bm < BM; ++bm) {
@@ -393,41 +422,45 @@ __global__ __launch_bounds__(GRAM_THREADS, 1) void gram_kernel(
           for (int r = 0; r < 32; ++r) {
             const int il = wm_ * 128 + bm * 32 + r;
             const int64_t i = i_base + il;
-            if (i >= T) break;
+            if (i >= rows_out) break;
             if (diag && il >= jl) continue;  // diagonal tile: strict upper half
             const float v = -2.f * src[r];
-            S[i * ldS + j] = v > 0.f ? v : 0.f;
+            // band mode: a field's distance to itself is stored as 0, as the
+            // mirrored pass stores it in the symmetric mode
+            S[i * ldS + j] = (BAND && a_row0 + i == j) ? 0.f : (v > 0.f ? v : 0.f);
           }
         }
       }
     }
-    // (j, i): 8 threads per (column, row half) write 32 consecutive i
-    for (int run = tid >> 3; run < WAVES_M * TILE; run += GRAM_THREADS / 8) {
-      const int jl = run / WAVES_M, wm_ = run % WAVES_M;
-      const int wn_ = jl / WT_N, c = jl % WT_N;
-      const int64_t j = j_base + jl;
-      if (j >= T) continue;
-      const int q = tid & 7;
-      const int il0 = wm_ * 128 + bm * 32 + 4 * q;
-      const int64_t i0 = i_base + il0;
-      const f32x4 g = *(const f32x4*)(stg + (wm_ * WAVES_N + wn_) * WT_N * EPI_PITCH +
-                                       c * EPI_PITCH + 4 * q);
-      float f[4];
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const float v = -2.f * g[e];
-        f[e] = v > 0.f ? v : 0.f;
-      }
-      float* dst = S + j * ldS + i0;
-      if (!diag && i0 + 3 < T) {
-        *(f32x4*)dst = f32x4{f[0], f[1], f[2], f[3]};
-      } else {
+    // (j, i): 8 threads per (column, row half) write 32 consecutive i (symmetric mode only)
+    if constexpr (!BAND) {
+      for (int run = tid >> 3; run < WAVES_M * TILE; run += GRAM_THREADS / 8) {
+        const int jl = run / WAVES_M, wm_ = run % WAVES_M;
+        const int wn_ = jl / WT_N, c = jl % WT_N;
+        const int64_t j = j_base + jl;
+        if (j >= T) continue;
+        const int q = tid & 7;
+        const int il0 = wm_ * 128 + bm * 32 + 4 * q;
+        const int64_t i0 = i_base + il0;
+        const f32x4 g = *(const f32x4*)(stg + (wm_ * WAVES_N + wn_) * WT_N * EPI_PITCH +
+                                         c * EPI_PITCH + 4 * q);
+        float f[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const int il = il0 + e;
-          if (i0 + e >= T) continue;
-          if (!diag || il < jl) dst[e] = f[e];
-          else if (il == jl) dst[e] = 0.f;
+          const float v = -2.f * g[e];
+          f[e] = v > 0.f ? v : 0.f;
+        }
+        float* dst = S + j * ldS + i0;
+        if (!diag && i0 + 3 < T) {
+          *(f32x4*)dst = f32x4{f[0], f[1], f[2], f[3]};
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int il = il0 + e;
+            if (i0 + e >= T) continue;
+            if (!diag || il < jl) dst[e] = f[e];
+            else if (il == jl) dst[e] = 0.f;
+          }
         }
       }
     }
@@ -440,25 +473,38 @@ __global__ __launch_bounds__(GRAM_THREADS, 1) void gram_kernel(
 hipError_t launch_gram(const void* xc, const float* ncs, int64_t T, int64_t Tpad,
                        int64_t Dpad, int nb, int64_t ntiles, int precision,
                        float* S, int64_t ldS, hipStream_t s) {
+  return launch_gram_band(xc, ncs, T, Tpad, Dpad, nb, ntiles, precision, -1, 0, 0, S, ldS, s);
+}
+
+hipError_t launch_gram_band(const void* xc, const float* ncs, int64_t T, int64_t Tpad,
+                            int64_t Dpad, int nb, int64_t ntiles, int precision,
+                            int64_t a_row0, int nbi, int64_t rows_out, float* S,
+                            int64_t ldS, hipStream_t s) {
   const int64_t pitch = Dpad * elem_bytes(precision);
   const int nstages = (int)(Dpad / stage_k(precision));
   const int64_t per = (ntiles + NUM_XCD - 1) / NUM_XCD;
   dim3 grid((unsigned)(per * NUM_XCD));
   const char* x = (const char*)xc;
+  const bool band = a_row0 >= 0;
+  if (!band) rows_out = T;
+#define TRAKNN_GRAM_LAUNCH(P, B)                                                          \
+  hipLaunchKernelGGL((gram_kernel<P, B>), grid, dim3(GRAM_THREADS), 0, s, x, pitch, nstages, \
+                     ncs, T, Tpad, nb, ntiles, a_row0, nbi, rows_out, S, ldS)
   switch (precision) {
     case TRAKNN_FP32:
-      hipLaunchKernelGGL(gram_kernel<TRAKNN_FP32>, grid, dim3(GRAM_THREADS), 0,
-                         s, x, pitch, nstages, ncs, T, Tpad, nb, ntiles, S, ldS);
+      if (band) TRAKNN_GRAM_LAUNCH(TRAKNN_FP32, true);
+      else TRAKNN_GRAM_LAUNCH(TRAKNN_FP32, false);
       break;
     case TRAKNN_BF16X3:
-      hipLaunchKernelGGL(gram_kernel<TRAKNN_BF16X3>, grid, dim3(GRAM_THREADS),
-                         0, s, x, pitch, nstages, ncs, T, Tpad, nb, ntiles, S, ldS);
+      if (band) TRAKNN_GRAM_LAUNCH(TRAKNN_BF16X3, true);
+      else TRAKNN_GRAM_LAUNCH(TRAKNN_BF16X3, false);
       break;
     default:
-      hipLaunchKernelGGL(gram_kernel<TRAKNN_FP16>, grid, dim3(GRAM_THREADS), 0,
-                         s, x, pitch, nstages, ncs, T, Tpad, nb, ntiles, S, ldS);
+      if (band) TRAKNN_GRAM_LAUNCH(TRAKNN_FP16, true);
+      else TRAKNN_GRAM_LAUNCH(TRAKNN_FP16, false);
       break;
   }
+#undef TRAKNN_GRAM_LAUNCH
   return hipGetLastError();
 }
 

@@ -51,12 +51,14 @@ struct traknn_plan_s {
   traknn_config cfg;
   int64_t T, D;
   int64_t Dpad;      // D rounded up to the Gram stage depth (zero padded)
-  int64_t Tpad;      // T rounded up to GRAM_TILE (zero rows)
-  int64_t ldS;       // row stride of the T x T distance matrix, floats
+  int64_t Tpad;      // T rounded up to GRAM_TILE, plus one tile in band mode (zero rows)
+  int64_t ldS;       // row stride of the distance matrix (or band), floats
   int64_t np0;       // T - L_min + 1: rows of every output block
   int NL;            // L_max - L_min + 1
-  int nb;            // Tpad / GRAM_TILE
+  int nb;            // ceil(T / GRAM_TILE) block-columns
   int64_t ntiles;    // nb (nb + 1) / 2 upper-triangular tile pairs
+  int64_t rb;        // band mode: trajectory rows per pass (0: whole matrix)
+  int64_t band_rows; // band mode: rows of S held, rb + L_max - 1 (at most T)
   int tchunks;       // ceil(T / COLSTAT_ROWS)
   int win_splits;    // column splits (waves) per window row block (W)
   traknn::Layout lay;
@@ -81,6 +83,13 @@ hipError_t launch_centre_convert(const float* X, int64_t ldx, int64_t T,
 hipError_t launch_gram(const void* xc, const float* ncs, int64_t T, int64_t Tpad,
                        int64_t Dpad, int nb, int64_t ntiles, int precision,
                        float* S, int64_t ldS, hipStream_t s);
+// Band mode: rows a_row0 .. a_row0 + rows_out - 1 (nbi = ceil(rows_out / 256)
+// block-rows, ntiles = nbi * nb) against every column, into S whose row 0 is
+// field a_row0. a_row0 must be a multiple of 4 and a_row0 + nbi * 256 <= Tpad.
+hipError_t launch_gram_band(const void* xc, const float* ncs, int64_t T, int64_t Tpad,
+                            int64_t Dpad, int nb, int64_t ntiles, int precision,
+                            int64_t a_row0, int nbi, int64_t rows_out, float* S,
+                            int64_t ldS, hipStream_t s);
 // window_topk.hip
 hipError_t launch_window_topk(const float* S, int64_t ldS, int64_t T, int L_min,
                               int L_max, int k, int splits, double* part_d,
@@ -88,6 +97,17 @@ hipError_t launch_window_topk(const float* S, int64_t ldS, int64_t T, int L_min,
 hipError_t launch_merge(const double* part_d, const int32_t* part_i, int64_t T,
                         int L_min, int L_max, int k, int splits, int32_t* idx,
                         double* dist, hipStream_t s);
+// Band mode: S holds rows s0 .. s_end - 1 (its row 0 is row s0); the lists of
+// trajectory rows t0 .. t0 + nt - 1 (counted for L_min; fewer for longer L)
+// go to partial lists indexed from t0, which launch_merge_band combines into
+// rows t0 .. of idx and dist.
+hipError_t launch_window_band(const float* S, int64_t ldS, int64_t T, int L_min,
+                              int L_max, int k, int splits, int64_t s0, int64_t s_end,
+                              int64_t t0, int64_t nt, double* part_d, int32_t* part_i,
+                              hipStream_t s);
+hipError_t launch_merge_band(const double* part_d, const int32_t* part_i, int64_t T,
+                             int L_min, int L_max, int k, int splits, int64_t t0, int64_t nt,
+                             int32_t* idx, double* dist, hipStream_t s);
 hipError_t launch_score(const double* dist, int64_t T, int L_min, int L_max,
                         int k, double* scores, hipStream_t s);
 hipError_t launch_score_prefix(const double* dist, int64_t T, int L_min, int L_max,

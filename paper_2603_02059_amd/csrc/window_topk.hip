@@ -16,6 +16,10 @@
 // is one compare per lane against that row's bound and one ballot; the rare
 // insertions shift a sorted list held one entry per lane.
 //
+// In band mode (row-batched streaming) S holds only rows s0 .. s_end - 1 of the
+// matrix, and a launch covers the trajectory rows row_lo .. row_hi - 1 whose
+// windows lie inside them; its partial lists are indexed from row_lo.
+//
 // A multi-length request (L = L_min .. L_max) runs the kernel once per length
 // on the same distance matrix, each with its own lists and exclusion zone
 // |i - j| >= L; the merge kernel then combines, per length and row, the W
@@ -157,8 +161,9 @@ __device__ __forceinline__ void seed_row(double d, int c, bool valid, int k, dou
 // a few per row block) skip the per-lane validity tests.
 template <int L>
 __global__ __launch_bounds__(1024) void window1_kernel(
-    const float* __restrict__ S, int64_t ldS, int T, int k, int W, int64_t split_stride,
-    double* __restrict__ part_d, int32_t* __restrict__ part_i) {
+    const float* __restrict__ S, int64_t ldS, int T, int s0, int s_end, int row_lo,
+    int row_hi, int k, int W, int64_t split_stride, double* __restrict__ part_d,
+    int32_t* __restrict__ part_i) {
   constexpr int R = W1_ROWS;
   constexpr int U = W1_GROUP;
   constexpr int M = R + L - 1;
@@ -174,9 +179,9 @@ __global__ __launch_bounds__(1024) void window1_kernel(
   if (threadIdx.x < R) shb[threadIdx.x] = (unsigned long long)__double_as_longlong(__builtin_huge_val());
   __syncthreads();  // the only workgroup barrier: the waves' trip counts differ
 
-  const int npL = T - L + 1;
-  const int r0 = blockIdx.x * R;
-  const int nrows = npL - r0 < R ? npL - r0 : R;  // rows of this block
+  const int npL = T - L + 1;  // candidate trajectories (columns)
+  const int r0 = row_lo + (int)blockIdx.x * R;
+  const int nrows = row_hi - r0 < R ? row_hi - r0 : R;  // rows of this block
   const int64_t dlo = -(int64_t)(r0 + R - 1);
   const int64_t NC = ((int64_t)npL + R - 1 + 63) / 64;
   const int64_t cb = (int64_t)split * NC / W, ce = (int64_t)(split + 1) * NC / W;
@@ -194,8 +199,8 @@ __global__ __launch_bounds__(1024) void window1_kernel(
     const int64_t dc = dlo + 64 * c;
     int64_t stride = ldS + 1;
     asm volatile("" : "+s"(stride));
-    const float* p = S + ((int64_t)r0 * stride + dc + lane);
-    const bool inb = r0 + dc >= 0 && (int64_t)r0 + M - 1 < T && r0 + M - 1 + dc + 63 < T;
+    const float* p = S + ((int64_t)(r0 - s0) * ldS + r0 + dc + lane);
+    const bool inb = r0 + dc >= 0 && r0 + M - 1 < s_end && r0 + M - 1 + dc + 63 < T;
     if (inb) {
 #pragma unroll
       for (int m = 0; m < M; ++m) {
@@ -203,7 +208,7 @@ __global__ __launch_bounds__(1024) void window1_kernel(
         p += stride;
       }
     } else {
-      int rows_in = T - r0;  // rows r0 + m with m < rows_in exist
+      int rows_in = s_end - r0;  // rows r0 + m with m < rows_in are held
       int64_t Tl = T;
       asm volatile("" : "+s"(rows_in), "+s"(Tl));
       int64_t col = r0 + dc + lane;  // column of row r0 + m, stepped with m
@@ -309,10 +314,10 @@ __global__ __launch_bounds__(1024) void window1_kernel(
     else
       scan_chunk(c, std::true_type{});
   }
-  // partial lists: part[(split * split_stride + row) * k + q]; a range with no
-  // chunk leaves its lists empty
+  // partial lists: part[(split * split_stride + row - row_lo) * k + q]; a
+  // range with no chunk leaves its lists empty
   for (int s = 0; s < nrows; ++s) {
-    const int row = r0 + s;
+    const int row = r0 - row_lo + s;
     if (lane < k) {
       const int64_t o = ((int64_t)split * split_stride + row) * k + lane;
       part_d[o] = cb < ce ? ld[s * k + lane] : __builtin_huge_val();
@@ -321,28 +326,31 @@ __global__ __launch_bounds__(1024) void window1_kernel(
   }
 }
 
-// Row blocks of length L: ceil((T - L + 1) / W1_ROWS) workgroups of W waves.
+// Row blocks of length L: ceil((row_hi - row_lo) / W1_ROWS) workgroups of W waves.
 template <int L>
-hipError_t launch_win1(const float* S, int64_t ldS, int T, int k, int W, int64_t split_stride,
-                       double* pd, int32_t* pi, hipStream_t s) {
+hipError_t launch_win1(const float* S, int64_t ldS, int T, int s0, int s_end, int row_lo,
+                       int row_hi, int k, int W, int64_t split_stride, double* pd,
+                       int32_t* pi, hipStream_t s) {
   const size_t lds = window1_lds_bytes(L, k, W);
-  const unsigned blocks = (unsigned)((T - L + 1 + W1_ROWS - 1) / W1_ROWS);
+  const unsigned blocks = (unsigned)((row_hi - row_lo + W1_ROWS - 1) / W1_ROWS);
   hipLaunchKernelGGL((window1_kernel<L>), dim3(blocks), dim3(64 * W), lds, s, S, ldS, T,
-                     k, W, split_stride, pd, pi);
+                     s0, s_end, row_lo, row_hi, k, W, split_stride, pd, pi);
   return hipGetLastError();
 }
 
 __global__ __launch_bounds__(256) void merge_kernel(
     const double* __restrict__ part_d, const int32_t* __restrict__ part_i,
-    int T, int np0, int Lmin, int NL, int k, int W, int32_t* __restrict__ idx,
-    double* __restrict__ dist) {
+    int T, int np0, int Lmin, int NL, int k, int W, int t0, int nt,
+    int32_t* __restrict__ idx, double* __restrict__ dist) {
+  // rows t0 .. t0 + nt - 1 of every length; partial lists indexed from t0
   const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (g >= (int64_t)NL * np0) return;
-  const int li = (int)(g / np0);
-  const int t = (int)(g % np0);
+  if (g >= (int64_t)NL * nt) return;
+  const int li = (int)(g / nt);
+  const int tr = (int)(g % nt);
+  const int t = t0 + tr;
   const int npL = T - (Lmin + li) + 1;
-  int32_t* oi = idx + g * k;
-  double* od = dist + g * k;
+  int32_t* oi = idx + ((int64_t)li * np0 + t) * k;
+  double* od = dist + ((int64_t)li * np0 + t) * k;
   if (t >= npL) {
     for (int q = 0; q < k; ++q) {
       oi[q] = -1;
@@ -359,7 +367,7 @@ __global__ __launch_bounds__(256) void merge_kernel(
     int bi = INT_MAX;
     for (int w = 0; w < W; ++w) {
       if (pos[w] >= k) continue;
-      const int64_t o = (((int64_t)w * NL + li) * np0 + t) * k + pos[w];
+      const int64_t o = (((int64_t)w * NL + li) * nt + tr) * k + pos[w];
       const double d = part_d[o];
       const int i = part_i[o];
       if (best < 0 || key_less(d, i, bd, bi)) {
@@ -419,19 +427,30 @@ size_t window1_lds_bytes(int L, int k, int W) {
 hipError_t launch_window_topk(const float* S, int64_t ldS, int64_t T, int L_min,
                               int L_max, int k, int splits, double* part_d,
                               int32_t* part_i, hipStream_t s) {
-  const int64_t np0 = T - L_min + 1;
+  return launch_window_band(S, ldS, T, L_min, L_max, k, splits, 0, T, 0, T - L_min + 1,
+                            part_d, part_i, s);
+}
+
+hipError_t launch_window_band(const float* S, int64_t ldS, int64_t T, int L_min,
+                              int L_max, int k, int splits, int64_t s0, int64_t s_end,
+                              int64_t t0, int64_t nt, double* part_d, int32_t* part_i,
+                              hipStream_t s) {
   const int NL = L_max - L_min + 1;
-  // partial lists: [split][length][row][k]
-  const int64_t split_stride = (int64_t)NL * np0;
+  // partial lists: [split][length][row - t0][k]
+  const int64_t split_stride = (int64_t)NL * nt;
   for (int L = L_min; L <= L_max; ++L) {
-    const int64_t off = (int64_t)(L - L_min) * np0 * k;
+    const int64_t off = (int64_t)(L - L_min) * nt * k;
     double* pd = part_d + off;
     int32_t* pi = part_i + off;
+    // rows of this length in [t0, t0 + nt): those with t <= T - L
+    const int64_t hi = t0 + nt < T - L + 1 ? t0 + nt : T - L + 1;
+    if (hi <= t0) continue;  // none (the merge marks them non-existent)
+    const int a = (int)s0, b = (int)s_end, lo = (int)t0, h = (int)hi;
     hipError_t e;
     switch (L) {
 #define TRAKNN_WIN1_CASE(n) \
   case n:                   \
-    e = launch_win1<n>(S, ldS, (int)T, k, splits, split_stride, pd, pi, s); \
+    e = launch_win1<n>(S, ldS, (int)T, a, b, lo, h, k, splits, split_stride, pd, pi, s); \
     break;
       TRAKNN_WIN1_CASE(1)
       TRAKNN_WIN1_CASE(2)
@@ -461,12 +480,19 @@ hipError_t launch_window_topk(const float* S, int64_t ldS, int64_t T, int L_min,
 hipError_t launch_merge(const double* part_d, const int32_t* part_i, int64_t T,
                         int L_min, int L_max, int k, int splits, int32_t* idx,
                         double* dist, hipStream_t s) {
+  return launch_merge_band(part_d, part_i, T, L_min, L_max, k, splits, 0, T - L_min + 1, idx,
+                           dist, s);
+}
+
+hipError_t launch_merge_band(const double* part_d, const int32_t* part_i, int64_t T,
+                             int L_min, int L_max, int k, int splits, int64_t t0, int64_t nt,
+                             int32_t* idx, double* dist, hipStream_t s) {
   const int np0 = (int)(T - L_min + 1);
   const int NL = L_max - L_min + 1;
-  const int64_t n = (int64_t)NL * np0;
+  const int64_t n = (int64_t)NL * nt;
   hipLaunchKernelGGL(merge_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256),
-                     0, s, part_d, part_i, (int)T, np0, L_min, NL, k, splits,
-                     idx, dist);
+                     0, s, part_d, part_i, (int)T, np0, L_min, NL, k, splits, (int)t0,
+                     (int)nt, idx, dist);
   return hipGetLastError();
 }
 

@@ -183,11 +183,16 @@ class Plan:
     """A TRAKNN plan plus its device workspace, reusable across calls."""
 
     def __init__(self, T: int, D: int, L_min: int, L_max: int | None = None,
-                 k: int = 10, precision: str | int = "bf16x3", device=None):
+                 k: int = 10, precision: str | int = "bf16x3", device=None,
+                 row_batch: int = 0):
+        """row_batch > 0 (a multiple of 8) streams the distance matrix in bands
+        of row_batch trajectory rows instead of holding all T x T of it."""
         L_max = L_min if L_max is None else L_max
         self.T, self.D, self.L_min, self.L_max, self.k = T, D, L_min, L_max, k
+        self.row_batch = row_batch
         self.precision = PRECISIONS[precision] if isinstance(precision, str) else precision
-        self.handle, self.ws_bytes = traknn_plan(T, D, L_min, L_max, k, self.precision)
+        self.handle, self.ws_bytes = traknn_plan(T, D, L_min, L_max, k, self.precision,
+                                                 row_batch)
         self.device = torch.device(device if device is not None else "cuda")
         self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
         self.NL = L_max - L_min + 1
@@ -252,10 +257,11 @@ class Plan:
 
 
 def knn(X: torch.Tensor, L: int, k: int, precision: str = "bf16x3",
-        L_max: int | None = None):
+        L_max: int | None = None, row_batch: int = 0):
     """Neighbour lists (idx [NL, n', k] int32, dist [NL, n', k] float64)."""
     X = _as_fields(X)
-    p = Plan(X.shape[0], X.shape[1], L, L_max, k, precision, device=X.device)
+    p = Plan(X.shape[0], X.shape[1], L, L_max, k, precision, device=X.device,
+             row_batch=row_batch)
     try:
         return p.knn(X)
     finally:

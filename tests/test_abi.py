@@ -54,7 +54,10 @@ def _plan_code(**kw):
     (dict(T=0), -1), (dict(D=0), -1), (dict(L_min=0, L_max=0), -1),
     (dict(L_min=4, L_max=3), -1), (dict(L_min=17, L_max=17), -1),
     (dict(k=0), -1), (dict(k=65), -1), (dict(precision=3), -1), (dict(precision=-1), -1),
-    (dict(row_batch=128), -2), (dict(L_min=2, L_max=5), -2),
+    (dict(L_min=2, L_max=5), -2),
+    # band mode: row_batch a non-negative multiple of 8
+    (dict(row_batch=128), 0), (dict(row_batch=8), 0), (dict(row_batch=4096), 0),
+    (dict(row_batch=-8), -1), (dict(row_batch=12), -1), (dict(row_batch=1), -1),
     (dict(L_min=1, L_max=16, k=64), 0), (dict(L_min=16, L_max=16, k=64), 0),
     # n' = T - L + 1 must leave k candidates beyond the exclusion zone
     (dict(T=6, D=1, L_min=2, L_max=2, k=2), 0), (dict(T=6, D=1, L_min=2, L_max=2, k=3), -1),
@@ -89,6 +92,26 @@ def test_workspace_sizes():
         assert _plan_code(precision=prec)[0] == 0
     _, ws_fp16 = _plan_code(T=27394, D=8192, L_min=5, L_max=5, k=10, precision=2)
     assert ws_fp16 < ws_full
+
+
+def test_band_workspace():
+    # band mode holds row_batch + L_max - 1 rows of S (not T), plus one extra
+    # zero tile of centred fields and norms
+    T, D, L, k = 27394, 8192, 5, 10
+    _, ws_full = _plan_code(T=T, D=D, L_min=L, L_max=L, k=k)
+    rb = 4088
+    _, ws_band = _plan_code(T=T, D=D, L_min=L, L_max=L, k=k, row_batch=rb)
+    ldS = (T + 63) // 64 * 64
+    assert ws_band < ws_full - (T - rb - L + 1) * ldS * 4 + 2 * (256 * D * 4 + 16 * 256 * 4)
+    assert ws_band >= (rb + L - 1) * ldS * 4 + (T + 255) // 256 * 256 * D * 4
+    # T = 2^20: the whole matrix (4 TiB) does not fit one GPU, a band does
+    _, ws_big = _plan_code(T=1 << 20, D=1024, L_min=L, L_max=L, k=k)
+    _, ws_big_band = _plan_code(T=1 << 20, D=1024, L_min=L, L_max=L, k=k, row_batch=4088)
+    assert ws_big > 4 * (1 << 40)
+    assert ws_big_band < 40 * (1 << 30)
+    # a row_batch beyond the rows is one pass over a band of all T rows
+    _, ws_one = _plan_code(row_batch=1 << 16)
+    assert ws_one >= 512 * 512 * 4
 
 
 class _FakeDev:

@@ -1,0 +1,143 @@
+"""GPU parity of band mode (row-batched streaming of the distance matrix).
+
+With ``row_batch`` > 0 the library computes the matrix in bands of
+row_batch + L_max - 1 rows against all columns and never holds all of it. The
+results must meet the same bar as the whole-matrix mode: the oracle's lists
+and scores within the precision's tolerance, on every row at small sizes and
+on sampled rows at large ones, for ragged passes (a last pass of one row, a
+band that spans a partial 256-row block-row, passes of 8 rows, one pass
+covering everything) and for multi-length sweeps. At T = 270000 the whole
+matrix (292 GB) exceeds the GPU's memory and only band mode can run.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2603_02059_amd import synth
+from tests.parity import check_rows, gram_norm_tol, precision_tol
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _run(Xn, L, k, prec, row_batch, L_max=None):
+    from paper_2603_02059_amd import traknn as tk
+    X = torch.from_numpy(np.ascontiguousarray(Xn, dtype=np.float32)).cuda()
+    p = tk.Plan(X.shape[0], X.shape[1], L, L_max, k, prec, row_batch=row_batch)
+    idx, dist = p.knn(X)
+    s = p.score(dist)
+    torch.cuda.synchronize()
+    out = idx.cpu().numpy(), dist.cpu().numpy(), s.cpu().numpy()
+    p.close()
+    del X
+    torch.cuda.empty_cache()
+    return out
+
+
+def _check_all_rows(idx, dist, s, L):
+    n = idx.shape[0]
+    t = np.arange(n)[:, None]
+    assert np.all((idx >= 0) & (idx < n)), "index out of range"
+    assert np.all(np.abs(idx - t) >= L), "exclusion zone violated"
+    srt = np.sort(idx, axis=1)
+    assert np.all(srt[:, 1:] != srt[:, :-1]), "duplicate neighbour"
+    d0, d1 = dist[:, :-1], dist[:, 1:]
+    i0, i1 = idx[:, :-1], idx[:, 1:]
+    assert np.all((d0 < d1) | ((d0 == d1) & (i0 < i1))), "list not in (distance, index) order"
+    np.testing.assert_allclose(s, dist.mean(axis=1), rtol=1e-14)
+
+
+@pytest.mark.parametrize("T,D,L,k,prec,rb", [
+    (700, 1000, 4, 7, "bf16x3", 248),    # 251-row bands: one block-row each
+    (700, 1000, 4, 7, "fp32", 8),        # 88 passes of 8 rows (11-row bands)
+    (613, 77, 6, 3, "fp16", 64),
+    (520, 300, 16, 64, "bf16x3", 504),   # 2 passes, the second of one row
+    (512, 128, 5, 10, "bf16x3", 1 << 16),  # one pass over all rows
+    (300, 5, 2, 9, "fp32", 40),
+])
+def test_band_parity(T, D, L, k, prec, rb):
+    _say(f"[gpu-band] T={T} D={D} L={L} k={k} prec={prec} row_batch={rb}")
+    Xn, _ = synth.make_fields(T, 1, D, sigma=2.0, n_events=2, event_len=L, seed=T + D + 1)
+    idx, dist, s = _run(Xn, L, k, prec, rb)
+    n = T - L + 1
+    ref = oracle.knn(Xn, L, k)
+    Dm = oracle.traj_dist(Xn, L)
+    stats = check_rows(Xn, L, k, np.arange(n), idx[0], dist[0], s[0], precision_tol(prec),
+                       ref=(ref[0], ref[1], ref[2], ref[3], Dm),
+                       norm_tol=gram_norm_tol(prec, D))
+    _say(f"  {stats}")
+    _check_all_rows(idx[0], dist[0], s[0], L)
+
+
+def test_band_multi_length_sweep():
+    T, D, Lmax, k, rb = 600, 200, 6, 5, 96
+    _say(f"[gpu-band] sweep L=1..{Lmax} T={T} D={D} row_batch={rb}")
+    Xn, _ = synth.make_fields(T, 10, 20, sigma=2.0, n_events=3, event_len=4, seed=5)
+    idx, dist, s = _run(Xn, 1, k, "bf16x3", rb, L_max=Lmax)
+    S = oracle.snapshot_dist(Xn)
+    for L in range(1, Lmax + 1):
+        n = T - L + 1
+        Dm = oracle.traj_dist_from_snapshot(S, L)
+        ref = oracle.knn_from_rows(Dm, np.arange(n), L, k)
+        stats = check_rows(Xn, L, k, np.arange(n), idx[L - 1, :n], dist[L - 1, :n],
+                           s[L - 1, :n], 1e-5, ref=ref + (Dm,),
+                           norm_tol=gram_norm_tol("bf16x3", D))
+        _say(f"  L={L}: {stats}")
+        assert np.all(idx[L - 1, n:] == -1) and np.all(np.isinf(dist[L - 1, n:]))
+        assert np.all(np.isnan(s[L - 1, n:]))
+
+
+def test_band_full_workload():
+    """T = 27394 daily 64 x 128 fields, L = 5, k = 10, BF16x3, passes of 4088
+    rows (4092-row bands, 16 block-rows each): every row's list is valid,
+    sampled rows match the oracle, and the scores match the whole-matrix mode."""
+    w = synth.WORKLOADS["full"]
+    rb = 4088
+    _say(f"[gpu-band] full T={w.T} D={w.D} L={w.L} k={w.k} row_batch={rb}")
+    Xn, starts = synth.make_workload(w)
+    idx, dist, s = _run(Xn, w.L, w.k, "bf16x3", rb)
+    idx, dist, s = idx[0], dist[0], s[0]
+    _check_all_rows(idx, dist, s, w.L)
+    n = idx.shape[0]
+    rows = set(np.linspace(0, n - 1, 24).astype(int).tolist())
+    # rows at pass boundaries
+    for b in range(rb, n, rb):
+        rows |= {b - 1, b}
+    rows |= {0, n - 1} | {st for st in starts if st < n}
+    rows = np.array(sorted(rows), dtype=np.int64)
+    stats = check_rows(Xn, w.L, w.k, rows, idx[rows], dist[rows], s[rows],
+                       precision_tol("bf16x3"))
+    _say(f"  {stats}")
+    # the whole-matrix mode: both within 1e-5 of the oracle, so within 2e-5
+    iw, dw, sw = _run(Xn, w.L, w.k, "bf16x3", 0)
+    np.testing.assert_allclose(s, sw[0], rtol=2e-5)
+    same = np.mean(np.all(np.sort(idx, 1) == np.sort(iw[0], 1), axis=1))
+    _say(f"  rows with the whole-matrix mode's neighbour set: {same:.5f}")
+
+
+def test_band_beyond_device_memory():
+    """T = 270000 fields of 32 x 32 (D = 1024), L = 5, k = 10: the whole
+    matrix needs more memory than the GPU has; band mode runs in ~18 GB."""
+    from paper_2603_02059_amd import traknn as tk
+    T, H, W, L, k, rb = 270000, 32, 32, 5, 10, 16376
+    total = torch.cuda.get_device_properties(0).total_memory
+    h, ws_whole = tk.traknn_plan(T, H * W, L, L, k, "bf16x3", 0)
+    tk.traknn_plan_destroy(h)
+    assert ws_whole > total, (ws_whole, total)
+    _say(f"[gpu-band] T={T} D={H * W} L={L} k={k} row_batch={rb} "
+         f"(whole matrix {ws_whole / 2**30:.0f} GiB > {total / 2**30:.0f} GiB)")
+    Xn, starts = synth.make_fields(T, H, W, sigma=2.0, n_events=20, event_len=5, seed=9)
+    idx, dist, s = _run(Xn, L, k, "bf16x3", rb)
+    idx, dist, s = idx[0], dist[0], s[0]
+    _check_all_rows(idx, dist, s, L)
+    n = T - L + 1
+    rows = np.unique(np.concatenate([np.linspace(0, n - 1, 8).astype(np.int64),
+                                     [rb - 1, rb, 7 * rb, n - 1], starts[:4]]))
+    stats = check_rows(Xn, L, k, rows, idx[rows], dist[rows], s[rows],
+                       precision_tol("bf16x3"), norm_tol=gram_norm_tol("bf16x3", H * W))
+    _say(f"  {stats}")
