@@ -6,8 +6,8 @@ results must meet the same bar as the whole-matrix mode: the oracle's lists
 and scores within the precision's tolerance, on every row at small sizes and
 on sampled rows at large ones, for ragged passes (a last pass of one row, a
 band that spans a partial 256-row block-row, passes of 8 rows, one pass
-covering everything) and for multi-length sweeps. At T = 270000 the whole
-matrix (292 GB) exceeds the GPU's memory and only band mode can run.
+covering everything) and for multi-length sweeps. At T = 300000 the whole
+matrix (360 GB) exceeds the GPU's 288 GiB and only band mode can run.
 """
 import numpy as np
 import pytest
@@ -121,10 +121,10 @@ def test_band_full_workload():
 
 
 def test_band_beyond_device_memory():
-    """T = 270000 fields of 32 x 32 (D = 1024), L = 5, k = 10: the whole
-    matrix needs more memory than the GPU has; band mode runs in ~18 GB."""
+    """T = 300000 fields of 32 x 32 (D = 1024), L = 5, k = 10: the whole
+    matrix needs more memory than the GPU has; band mode runs in ~21 GB."""
     from paper_2603_02059_amd import traknn as tk
-    T, H, W, L, k, rb = 270000, 32, 32, 5, 10, 16376
+    T, H, W, L, k, rb = 300000, 32, 32, 5, 10, 16376
     total = torch.cuda.get_device_properties(0).total_memory
     h, ws_whole = tk.traknn_plan(T, H * W, L, L, k, "bf16x3", 0)
     tk.traknn_plan_destroy(h)
