@@ -13,7 +13,9 @@ What is computed (paper, Section 3.2):
   * exclusion zone |t - j| >= L (e = L - 1);
   * Eq. 3: s_t = mean of the k smallest D_L(t, j) over candidates, ties by the
     smaller j;
-  * the gradient of sum_t w_t s_t with the neighbour sets held fixed.
+  * the gradient of sum_t w_t s_t with the neighbour sets held fixed;
+  * the local intrinsic dimension of Section 5.1 (Levina-Bickel maximum
+    likelihood kNN estimator) from the sorted neighbour distances.
 
 Pins (what ties this code to something other than itself) are in
 ``tests/test_oracle_pins.py``; every function here is pinned there.
@@ -63,10 +65,12 @@ def _load():
             lib.oracle_knn_rows.argtypes = [_f64p, _i64p, i64, i64, i32, i32, _i32p,
                                             _f64p, _f64p, _f64p]
             lib.oracle_score_grad.argtypes = [_f64p, i64, i64, i32, i32, _i32p, _f64p, _f64p]
+            lib.oracle_local_dim.argtypes = [_f64p, i64, i32, _f64p]
             lib.oracle_num_threads.argtypes = []
             for f in (lib.oracle_snapshot_dist, lib.oracle_traj_dist_from_snapshot,
                       lib.oracle_traj_dist_rows, lib.oracle_pair_traj_dist,
-                      lib.oracle_knn_rows, lib.oracle_score_grad, lib.oracle_num_threads):
+                      lib.oracle_knn_rows, lib.oracle_score_grad, lib.oracle_local_dim,
+                      lib.oracle_num_threads):
                 f.restype = ctypes.c_int
             _lib = lib
     return _lib
@@ -169,6 +173,18 @@ def knn_rows(X, L: int, k: int, rows):
     (idx, dist, score, gap, drows)."""
     drows = traj_dist_rows(X, L, rows)
     return knn_from_rows(drows, rows, L, k) + (drows,)
+
+
+def local_dim(dist) -> np.ndarray:
+    """Levina-Bickel maximum-likelihood local intrinsic dimension (the
+    estimator of Section 5.1) from sorted squared neighbour distances
+    ``dist`` [r, k]: out[:, q] is the estimate from the q + 1 nearest
+    (column 0, one neighbour, is NaN)."""
+    dist = np.ascontiguousarray(dist, dtype=np.float64)
+    r, k = dist.shape
+    out = np.empty((r, k), dtype=np.float64)
+    _check(_load().oracle_local_dim(dist, r, int(k), out), "local_dim")
+    return out
 
 
 def score_grad(X, L: int, k: int, idx, w) -> np.ndarray:

@@ -228,6 +228,34 @@ int oracle_score_grad(const double* X, int64_t T, int64_t D, int L, int k,
   return ORACLE_OK;
 }
 
+/* Local intrinsic dimension by the maximum-likelihood kNN estimator of Levina
+ * and Bickel (2004), which the paper applies to trajectories with k in
+ * {20, 30, 40} (Section 5.1, "Intrinsic dimension study"):
+ *   m_k(t) = [ 1/(k-1) * sum_{j=1}^{k-1} ln( T_k(t) / T_j(t) ) ]^{-1}
+ * with T_j(t) the Euclidean distance from t to its j-th nearest neighbour.
+ * The inputs are the sorted SQUARED distances dist[r*k + q] = T_{q+1}(t)^2
+ * of each row, so ln(T_k / T_j) = ln(dist_k / dist_j) / 2, each term taken
+ * as written (ratio first, then its logarithm), summed over j = 1..k'-1 in
+ * increasing order.
+ * Output out[r*k + q] = m_{k'}(t) for k' = q + 1 = 2..k (every prefix of the
+ * list is the k'-nearest list); out[r*k] (k' = 1, no ratio) is NaN.
+ * Degenerate rows follow IEEE arithmetic: a zero distance below a positive
+ * T_k' makes a term +inf and the estimate 0; T_k' = 0 gives NaN; k' equal
+ * distances give +inf. */
+int oracle_local_dim(const double* dist, int64_t nrows, int k, double* out) {
+  if (!dist || !out || nrows < 0 || k < 1) return ORACLE_EINVAL;
+  for (int64_t r = 0; r < nrows; ++r) {
+    const double* d = dist + r * k;
+    out[r * k] = NAN;
+    for (int kk = 2; kk <= k; ++kk) {
+      double sum = 0.0;
+      for (int j = 1; j <= kk - 1; ++j) sum += 0.5 * log(d[kk - 1] / d[j - 1]);
+      out[r * k + kk - 1] = 1.0 / (sum / (double)(kk - 1));
+    }
+  }
+  return ORACLE_OK;
+}
+
 /* OpenMP thread count actually used by the parallel loops above. */
 int oracle_num_threads(void) {
   int n = 1;

@@ -334,3 +334,52 @@ def test_rows_mode_matches_full():
     np.testing.assert_array_equal(drows, oracle.traj_dist(X, L)[rows])
     np.testing.assert_array_equal(idx, full[0][rows])
     np.testing.assert_array_equal(score, full[2][rows])
+
+
+# --- local intrinsic dimension (Section 5.1, Levina-Bickel MLE) -------------
+
+@pytest.mark.parametrize("d,k,c", [(1.0, 20, 3.0), (5.0, 30, 0.01), (18.0, 40, 1e4),
+                                   (2.5, 2, 1.0)])
+def test_local_dim_closed_form(d, k, c):
+    """Neighbour distances T_j = c j^(1/d) (the spacing of points of a
+    d-dimensional set of uniform density) give the closed form
+    m_k = (k - 1) d / ((k - 1) ln k - ln (k - 1)!), with ln (k - 1)! from
+    lgamma -- a different route from the oracle's sum of log-ratios."""
+    import math
+    j = np.arange(1, k + 1, dtype=np.float64)
+    sq = (c * j ** (1.0 / d)) ** 2  # squared distances, as the lists hold
+    m = oracle.local_dim(sq[None, :])[0]
+    assert np.isnan(m[0])
+    for kk in range(2, k + 1):
+        expect = (kk - 1) * d / ((kk - 1) * math.log(kk) - math.lgamma(kk))
+        assert m[kk - 1] == pytest.approx(expect, rel=1e-12)
+
+
+@pytest.mark.parametrize("d", [1, 2, 5, 8])
+def test_local_dim_recovers_known_dimension(d):
+    """Gaussian samples in a d-dimensional subspace of a 64-cell field, with
+    the oracle's own kNN (L = 1): the mean local estimate with k = 20,
+    debiased by (k - 2)/(k - 1) as Levina and Bickel note, is within 10% of d.
+    A dropped square-root halving would give 2d, a flipped ratio a negative
+    value."""
+    rng = np.random.default_rng(d)
+    N, k = 3000, 20
+    Q, _ = np.linalg.qr(rng.standard_normal((64, d)))
+    X = rng.standard_normal((N, d)) @ Q.T * 100.0 + 5000.0
+    _, dist, _, _ = oracle.knn(X, 1, k)
+    m = oracle.local_dim(dist)[:, k - 1]
+    assert abs(np.mean(m) * (k - 2) / (k - 1) - d) <= 0.1 * d
+
+
+def test_local_dim_scale_invariant_and_degenerate():
+    rng = np.random.default_rng(3)
+    dist = np.sort(rng.uniform(1.0, 50.0, (40, 12)), axis=1)
+    m = oracle.local_dim(dist)
+    np.testing.assert_allclose(oracle.local_dim(dist * 7.5e6), m, rtol=1e-12)
+    # duplicates below a positive k-th distance: estimate 0; all equal: +inf;
+    # all zero: NaN
+    deg = oracle.local_dim(np.array([[0.0, 0.0, 2.0, 3.0], [4.0, 4.0, 4.0, 4.0],
+                                     [0.0, 0.0, 0.0, 0.0]]))
+    assert deg[0, 2] == 0.0 and deg[0, 3] == 0.0 and np.isnan(deg[0, 1])
+    assert np.all(np.isinf(deg[1, 1:]))
+    assert np.all(np.isnan(deg[2]))
