@@ -166,6 +166,21 @@ int traknn_score(traknn_plan_t plan, const double* nbr_dist, double* scores,
 int traknn_score_prefix(traknn_plan_t plan, const double* nbr_dist, double* scores,
                         void* stream);
 
+/* Local intrinsic dimension of every trajectory for every k' = 1..k from one
+ * search: the maximum-likelihood kNN estimator of Levina and Bickel, which
+ * the paper applies to trajectories with k in {20, 30, 40} (Sec. 5.1,
+ * intrinsic dimension study). With the sorted squared distances of a list,
+ *   out[l][t][q] = 2 q / sum_{j<q} ln(nbr_dist[l][t][q] / nbr_dist[l][t][j])
+ * for k' = q + 1 = 2..k (the Euclidean log-ratio is half the squared one), in
+ * FP64. out[l][t][0] (k' = 1, no ratio) is NaN. Degenerate lists follow IEEE
+ * arithmetic: a zero distance below a positive k'-th gives 0, a zero k'-th
+ * distance NaN, k' equal distances +inf. Averaging over t (and over several
+ * k') gives the paper's mean local dimension; that reduction is the caller's.
+ *   nbr_dist [in]  as written by traknn_knn for the same plan.
+ *   out      [out] FP64 [L_max-L_min+1][T-L_min+1][k]; NaN in non-existent rows.
+ * Errors: INVALID_ARG, HIP. */
+int traknn_local_dim(traknn_plan_t plan, const double* nbr_dist, double* out, void* stream);
+
 /* Gradient of F = sum_t grad_scores[t] * s_t with respect to X, the neighbour
  * sets held fixed (differentiating Eq. 2 inside Eq. 3):
  *   dF/dx_a = (2/k) sum_t w_t sum_{j in N_t} sum_{m<L}

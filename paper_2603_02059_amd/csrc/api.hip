@@ -304,6 +304,13 @@ int traknn_score_prefix(traknn_plan_t plan, const double* nbr_dist, double* scor
                                       (hipStream_t)stream));
 }
 
+int traknn_local_dim(traknn_plan_t plan, const double* nbr_dist, double* out, void* stream) {
+  if (!plan || !nbr_dist || !out) return TRAKNN_ERR_INVALID_ARG;
+  const traknn_config& c = plan->cfg;
+  return fail_hip(launch_local_dim(nbr_dist, plan->T, c.L_min, c.L_max, c.k, out,
+                                   (hipStream_t)stream));
+}
+
 int traknn_score_backward(traknn_plan_t plan, const float* X, int64_t ldx,
                           const int32_t* nbr_idx, const double* grad_scores,
                           float* grad_X, int64_t ldg, void* workspace,

@@ -112,6 +112,8 @@ hipError_t launch_score(const double* dist, int64_t T, int L_min, int L_max,
                         int k, double* scores, hipStream_t s);
 hipError_t launch_score_prefix(const double* dist, int64_t T, int L_min, int L_max,
                                int k, double* out, hipStream_t s);
+hipError_t launch_local_dim(const double* dist, int64_t T, int L_min, int L_max, int k,
+                            double* out, hipStream_t s);
 // backward.hip
 hipError_t launch_backward(const float* X, int64_t ldx, int64_t T, int64_t D,
                            int L, int k, const int32_t* idx, const double* w,

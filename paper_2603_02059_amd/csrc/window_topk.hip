@@ -417,6 +417,31 @@ __global__ __launch_bounds__(256) void score_prefix_kernel(
   }
 }
 
+// Local intrinsic dimension of every trajectory (the maximum-likelihood kNN
+// estimator of Levina and Bickel that the paper applies with k in {20, 30,
+// 40}, Section 5.1), for every prefix k' of its sorted list:
+//   m_k' = 2 (k' - 1) / sum_{j<k'} ln(dist[k'-1] / dist[j]),
+// the Euclidean log-ratio being half the log-ratio of the squared distances.
+// out[0] (k' = 1, no ratio) and rows that do not exist are NaN; degenerate
+// lists follow IEEE arithmetic (a zero below a positive k'-th distance gives
+// 0, a zero k'-th distance NaN, k' equal distances +inf).
+__global__ __launch_bounds__(256) void local_dim_kernel(
+    const double* __restrict__ dist, int T, int np0, int Lmin, int NL, int k,
+    double* __restrict__ out) {
+  const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (g >= (int64_t)NL * np0) return;
+  const int li = (int)(g / np0);
+  const int t = (int)(g % np0);
+  const bool exists = t < T - (Lmin + li) + 1;
+  const double* d = dist + g * k;
+  out[g * k] = __builtin_nan("");
+  for (int q = 1; q < k; ++q) {
+    double s = 0.0;
+    for (int j = 0; j < q; ++j) s += log(d[q] / d[j]);
+    out[g * k + q] = exists ? 2.0 * (double)q / s : __builtin_nan("");
+  }
+}
+
 }  // namespace
 
 size_t window1_lds_bytes(int L, int k, int W) {
@@ -513,6 +538,16 @@ hipError_t launch_score_prefix(const double* dist, int64_t T, int L_min, int L_m
   const int64_t n = (int64_t)NL * np0;
   hipLaunchKernelGGL(score_prefix_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256),
                      0, s, dist, (int)T, np0, L_min, NL, k, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_local_dim(const double* dist, int64_t T, int L_min, int L_max, int k,
+                            double* out, hipStream_t s) {
+  const int np0 = (int)(T - L_min + 1);
+  const int NL = L_max - L_min + 1;
+  const int64_t n = (int64_t)NL * np0;
+  hipLaunchKernelGGL(local_dim_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                     dist, (int)T, np0, L_min, NL, k, out);
   return hipGetLastError();
 }
 

@@ -35,7 +35,7 @@ MAX_K = 64
 STAGES = ("centre_stats", "centre_convert", "gram", "window_topk", "merge")
 
 EXPORTS = ("traknn_plan", "traknn_plan_destroy", "traknn_knn", "traknn_score",
-           "traknn_score_prefix", "traknn_score_backward", "traknn_status_string", "traknn_set_timing",
+           "traknn_score_prefix", "traknn_local_dim", "traknn_score_backward", "traknn_status_string", "traknn_set_timing",
            "traknn_stage_times")
 
 
@@ -66,6 +66,7 @@ def _load() -> ctypes.CDLL:
     lib.traknn_knn.argtypes = [vp, vp, i64, vp, sz, vp, vp, vp]
     lib.traknn_score.argtypes = [vp, vp, vp, vp]
     lib.traknn_score_prefix.argtypes = [vp, vp, vp, vp]
+    lib.traknn_local_dim.argtypes = [vp, vp, vp, vp]
     lib.traknn_score_backward.argtypes = [vp, vp, i64, vp, vp, vp, i64, vp, sz, vp]
     lib.traknn_status_string.argtypes = [i32]
     lib.traknn_status_string.restype = ctypes.c_char_p
@@ -135,6 +136,11 @@ def traknn_score(plan, nbr_dist, scores, stream=None) -> None:
 def traknn_score_prefix(plan, nbr_dist, scores, stream=None) -> None:
     _ck(_lib.traknn_score_prefix(plan, _ptr(nbr_dist), _ptr(scores), _stream(stream)),
         "traknn_score_prefix")
+
+
+def traknn_local_dim(plan, nbr_dist, out, stream=None) -> None:
+    _ck(_lib.traknn_local_dim(plan, _ptr(nbr_dist), _ptr(out), _stream(stream)),
+        "traknn_local_dim")
 
 
 def traknn_score_backward(plan, X, ldx: int, nbr_idx, grad_scores, grad_X,
@@ -237,6 +243,15 @@ class Plan:
                                  device=self.device)
         traknn_score_prefix(self.handle, dist, scores, stream)
         return scores
+
+    def local_dim(self, dist: torch.Tensor, out=None, stream=None):
+        """Local intrinsic dimension (Levina-Bickel MLE) of every trajectory for
+        every k' = 1..k: [NL, n', k] float64 (column 0 is NaN)."""
+        if out is None:
+            out = torch.empty((self.NL, self.np0, self.k), dtype=torch.float64,
+                              device=self.device)
+        traknn_local_dim(self.handle, dist, out, stream)
+        return out
 
     def backward(self, X: torch.Tensor, idx: torch.Tensor, grad_scores: torch.Tensor,
                  grad_X=None, stream=None):

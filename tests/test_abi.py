@@ -145,6 +145,11 @@ def test_knn_argument_validation_enqueues_nothing():
         with pytest.raises(tk.TraknnError) as e:
             tk.traknn_score(h, None, Dd, stream=0)
         assert e.value.code == -1
+        for f in (tk.traknn_score_prefix, tk.traknn_local_dim):
+            for a, b in ((None, Dd), (Dd, None)):
+                with pytest.raises(tk.TraknnError) as e:
+                    f(h, a, b, stream=0)
+                assert e.value.code == -1, f
         with pytest.raises(tk.TraknnError) as e:
             tk.traknn_score_backward(h, X, 1024, I, None, W, 1024, W, ws, stream=0)
         assert e.value.code == -1

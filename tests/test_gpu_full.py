@@ -214,3 +214,40 @@ def test_backward_config():
     F = float(sn[rare].sum())
     euler = float(((X64 - X64.mean(axis=0)) * g).sum())
     assert abs(euler - 2 * F) <= 2e-5 * 2 * F, (euler, 2 * F)
+
+
+def test_local_dim_sweep():
+    """The intrinsic dimension study's shape (Section 5.1): one sweep over
+    L = 1..5 with k = 40 at the full size, the local dimension for every
+    k' <= 40; sampled rows against the oracle's lists and estimator, and the
+    mean local dimension over k' in {20, 30, 40} printed per L."""
+    from paper_2603_02059_amd import traknn as tk
+    w = synth.WORKLOADS["full"]
+    Xn, starts = _workload("full")
+    k, Lmax = 40, 5
+    _say(f"[gpu-full] local dimension sweep L=1..{Lmax} k={k} T={w.T} D={w.D}")
+    X = torch.from_numpy(Xn).cuda()
+    p = tk.Plan(w.T, w.D, 1, Lmax, k, "bf16x3")
+    idx, dist = p.knn(X)
+    ld = p.local_dim(dist)
+    torch.cuda.synchronize()
+    dist_h, ld_h = dist.cpu().numpy(), ld.cpu().numpy()
+    p.close()
+    del X
+    torch.cuda.empty_cache()
+    rng = np.random.default_rng(12)
+    for L in range(1, Lmax + 1):
+        n = w.T - L + 1
+        np.testing.assert_allclose(ld_h[L - 1, :n], oracle.local_dim(dist_h[L - 1, :n]),
+                                   rtol=1e-12)
+        assert np.all(np.isnan(ld_h[L - 1, n:]))
+        m = ld_h[L - 1, :n][:, [19, 29, 39]]
+        _say(f"  L={L}: mean local dimension {np.mean(m):.2f} +- {np.std(m):.2f}")
+        if L in (1, Lmax):
+            rows = np.unique(np.concatenate([rng.integers(0, n, 6), [0, n - 1]]))
+            r = oracle.knn_rows(Xn, L, k, rows)
+            ref = oracle.local_dim(r[1])
+            got = ld_h[L - 1][rows]
+            err = np.abs(got[:, 1:] - ref[:, 1:])
+            tol = 2.0 * ref[:, 1:] ** 2 * 1e-5 + 1e-12 * ref[:, 1:]
+            assert np.all(err <= tol), float(err.max())

@@ -271,3 +271,44 @@ def test_stage_timing():
     t = p.stage_times()
     assert set(t) == set(tk.STAGES) and all(v >= 0 for v in t.values())
     p.close()
+
+
+def _dim_tol(m_ref, eps):
+    # |d m| <= m^2 eps to first order when every distance of the list moves by
+    # at most a relative eps (m = 2(k'-1)/S and |dS| <= 2(k'-1) eps)
+    return 2.0 * np.abs(m_ref) ** 2 * eps + 1e-12 * np.abs(m_ref)
+
+
+def test_local_dim_every_k():
+    """Local intrinsic dimension (Section 5.1 estimator) for every k' <= 40
+    from one search: on the GPU's own lists it equals the oracle's estimator;
+    end to end against the oracle's lists it is within what the 1e-5
+    distance tolerance allows; crafted degenerate lists give the same NaN, 0
+    and +inf."""
+    tk = _tk()
+    w = synth.WORKLOADS["tiny"]
+    _say("[gpu] local intrinsic dimension k'=1..40")
+    Xn, _ = synth.make_workload(w)
+    X = torch.from_numpy(Xn).cuda()
+    k = 40
+    p = tk.Plan(w.T, w.D, w.L, w.L, k, "bf16x3")
+    idx, dist = p.knn(X)
+    ld = p.local_dim(dist)
+    rng = np.random.default_rng(8)
+    crafted = np.sort(rng.uniform(1.0, 2.0, (1, p.np0, k)), axis=2)
+    crafted[0, 0, :3] = 0.0          # duplicates below positive distances
+    crafted[0, 1, :] = 5.0           # all equal
+    crafted[0, 2, :] = 0.0           # all zero
+    crafted[0, 3, :] *= 1e9          # scale
+    ldc = p.local_dim(torch.from_numpy(crafted).cuda())
+    torch.cuda.synchronize()
+    dist_h, ld_h, ldc_h = dist.cpu().numpy()[0], ld.cpu().numpy()[0], ldc.cpu().numpy()[0]
+    p.close()
+    np.testing.assert_allclose(ld_h, oracle.local_dim(dist_h), rtol=1e-12)
+    np.testing.assert_allclose(ldc_h, oracle.local_dim(crafted[0]), rtol=1e-12)
+    assert np.all(np.isnan(ld_h[:, 0]))
+    ref = oracle.local_dim(oracle.knn(Xn, w.L, k)[1])
+    err = np.abs(ld_h[:, 1:] - ref[:, 1:])
+    assert np.all(err <= _dim_tol(ref[:, 1:], 1e-5)), float(err.max())
+    _say(f"  mean local dimension k'=20,30,40: "
+         f"{[round(float(np.mean(ld_h[:, q - 1])), 2) for q in (20, 30, 40)]}")
