@@ -165,7 +165,7 @@ int traknn_plan(const traknn_config* cfg, traknn_plan_t* out,
   p->nb = (int)((c.T + GRAM_TILE - 1) / GRAM_TILE);
   p->ntiles = (int64_t)p->nb * (p->nb + 1) / 2;
   p->band_rows = p->rb + c.L_max - 1 < c.T ? p->rb + c.L_max - 1 : c.T;
-  p->tchunks = (int)((c.T + COLSTAT_ROWS - 1) / COLSTAT_ROWS);
+  p->tchunks = colstat_chunks(c.T);
   if (!plan_window(p)) {
     delete p;
     return TRAKNN_ERR_UNSUPPORTED;

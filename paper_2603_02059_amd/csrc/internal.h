@@ -38,6 +38,14 @@ __host__ __device__ inline int64_t norm_chunks(int64_t Dpad) { return (Dpad + GR
 // Per-stage event slots for optional timing.
 constexpr int NUM_STAGES = 5;
 constexpr int COLSTAT_ROWS = 128;  // rows per partial column-sum block
+// The per-cell shift is the mean of at most COLSTAT_SAMPLE evenly strided rows
+// (rows 0, s, 2s, ... with s = ceil(T / COLSTAT_SAMPLE)).
+constexpr int64_t COLSTAT_SAMPLE = 2048;
+inline int64_t colstat_stride(int64_t T) { return (T + COLSTAT_SAMPLE - 1) / COLSTAT_SAMPLE; }
+inline int colstat_chunks(int64_t T) {
+  const int64_t s = colstat_stride(T);
+  return (int)(((T + s - 1) / s + COLSTAT_ROWS - 1) / COLSTAT_ROWS);
+}
 
 struct Layout {
   size_t mu_part, mu, ncs, xc, S, part_d, part_i;  // forward
@@ -59,7 +67,7 @@ struct traknn_plan_s {
   int64_t ntiles;    // nb (nb + 1) / 2 upper-triangular tile pairs
   int64_t rb;        // band mode: trajectory rows per pass (0: whole matrix)
   int64_t band_rows; // band mode: rows of S held, rb + L_max - 1 (at most T)
-  int tchunks;       // ceil(T / COLSTAT_ROWS)
+  int tchunks;       // partial column-sum blocks of the sampled rows
   int win_splits;    // column splits (waves) per window row block (W)
   traknn::Layout lay;
   // timing

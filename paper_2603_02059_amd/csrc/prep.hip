@@ -1,10 +1,14 @@
 // Centring, precision conversion and squared norms (the precomputed norms of
 // Algorithm 1, stage 1; Eq. 4).
 //
-// Distances are translation invariant, so the fields are centred per grid cell
+// Distances are translation invariant, so the fields are shifted per grid cell
 // before the Gram product: with ~1e5 Pa offsets the uncentred inner products
 // would cancel against the norms and lose every bit the reduced-precision
-// paths carry. Means and centred values are FP64. The squared norms are taken
+// paths carry. Any per-cell shift gives the same distances; the shift only has
+// to remove the offset. It is the FP64 mean over an evenly strided sample of
+// at most COLSTAT_SAMPLE rows (every row when T is at most that), which reads
+// a small fraction of X and lies within about sigma / sqrt(COLSTAT_SAMPLE) of
+// the full mean. Centred values are FP64. The squared norms are taken
 // per chunk of GRAM_CHUNK elements, in FP64, of exactly the vector the Gram
 // stage represents (FP32, FP16 or hi + lo), so that the Gram stage's
 // N_i + N_j - 2G, assembled chunk by chunk, is a distance between the same two
@@ -18,24 +22,26 @@
 namespace traknn {
 namespace {
 
-// Partial column sums over blocks of COLSTAT_ROWS rows: each thread sums 4
-// consecutive cells (one 16-byte load per row, 1 KB per wave and row), eight
-// rows in flight at a time, in a fixed order.
+// Partial column sums of the sampled rows (sample r is row r * stride) over
+// blocks of COLSTAT_ROWS samples: each thread sums 4 consecutive cells (one
+// 16-byte load per row, 1 KB per wave and row), eight rows in flight at a
+// time, in a fixed order.
 __global__ __launch_bounds__(256) void colsum_partial_kernel(
-    const float* __restrict__ X, int64_t ldx, int64_t T, int64_t D,
+    const float* __restrict__ X, int64_t ldx, int64_t nsamp, int64_t stride, int64_t D,
     double* __restrict__ part) {
   const int64_t c = 4 * ((int64_t)blockIdx.x * 256 + threadIdx.x);
   const int64_t r0 = (int64_t)blockIdx.y * COLSTAT_ROWS;
   if (c >= D) return;
-  const int64_t r1 = r0 + COLSTAT_ROWS < T ? r0 + COLSTAT_ROWS : T;
+  const int64_t r1 = r0 + COLSTAT_ROWS < nsamp ? r0 + COLSTAT_ROWS : nsamp;
+  const int64_t step = stride * ldx;  // floats between sampled rows
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
   if (c + 4 <= D) {
-    const float* p = X + r0 * ldx + c;
+    const float* p = X + r0 * step + c;
     int64_t r = r0;
     for (; r + 8 <= r1; r += 8) {
       float4 v[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = *(const float4*)(p + u * ldx);
+      for (int u = 0; u < 8; ++u) v[u] = *(const float4*)(p + u * step);
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         s0 += (double)v[u].x;
@@ -43,9 +49,9 @@ __global__ __launch_bounds__(256) void colsum_partial_kernel(
         s2 += (double)v[u].z;
         s3 += (double)v[u].w;
       }
-      p += 8 * ldx;
+      p += 8 * step;
     }
-    for (; r < r1; ++r, p += ldx) {
+    for (; r < r1; ++r, p += step) {
       const float4 v = *(const float4*)p;
       s0 += (double)v.x;
       s1 += (double)v.y;
@@ -54,7 +60,7 @@ __global__ __launch_bounds__(256) void colsum_partial_kernel(
     }
   } else {
     for (int64_t r = r0; r < r1; ++r) {
-      const float* p = X + r * ldx + c;
+      const float* p = X + r * step + c;
       s0 += (double)p[0];
       if (c + 1 < D) s1 += (double)p[1];
       if (c + 2 < D) s2 += (double)p[2];
@@ -67,16 +73,16 @@ __global__ __launch_bounds__(256) void colsum_partial_kernel(
   if (c + 3 < D) out[3] = s3;
 }
 
-// Fixed-order reduction of the partial sums -> per-cell mean.
+// Fixed-order reduction of the partial sums -> per-cell sample mean.
 __global__ __launch_bounds__(256) void colsum_reduce_kernel(
-    const double* __restrict__ part, int64_t T, int64_t D, int nchunks,
+    const double* __restrict__ part, int64_t nsamp, int64_t D, int nchunks,
     double* __restrict__ mu) {
   const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (c >= D) return;
   double s = 0.0;
 #pragma unroll 8
   for (int q = 0; q < nchunks; ++q) s += part[(int64_t)q * D + c];
-  mu[c] = s / (double)T;
+  mu[c] = s / (double)nsamp;
 }
 
 __device__ inline double wave_sum(double v) {
@@ -203,13 +209,15 @@ __global__ __launch_bounds__(256) void centre_convert_kernel(
 hipError_t launch_colstats(const float* X, int64_t ldx, int64_t T, int64_t D,
                            int tchunks, double* mu_part, double* mu,
                            hipStream_t s) {
+  const int64_t stride = colstat_stride(T);
+  const int64_t nsamp = (T + stride - 1) / stride;
   dim3 g1((unsigned)((D + 1023) / 1024), (unsigned)tchunks);
-  hipLaunchKernelGGL(colsum_partial_kernel, g1, dim3(256), 0, s, X, ldx, T, D,
+  hipLaunchKernelGGL(colsum_partial_kernel, g1, dim3(256), 0, s, X, ldx, nsamp, stride, D,
                      mu_part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(colsum_reduce_kernel, dim3((unsigned)((D + 255) / 256)),
-                     dim3(256), 0, s, mu_part, T, D, tchunks, mu);
+                     dim3(256), 0, s, mu_part, nsamp, D, tchunks, mu);
   return hipGetLastError();
 }
 
