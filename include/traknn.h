@@ -129,7 +129,8 @@ int traknn_plan(const traknn_config* cfg, traknn_plan_t* out,
 int traknn_plan_destroy(traknn_plan_t plan);
 
 /* Exact exclusion-zone kNN over trajectories (paper, Algorithm 1 stages 1-3:
- * Eq. 4 Gram distances for the upper-triangular tile pairs, Eq. 5 diagonal
+ * Eq. 4 Gram distances for the upper-triangular tile pairs -- or, in band
+ * mode, for each pass's rows against all columns -- Eq. 5 diagonal
  * recurrence, k smallest with |t - j| > e).
  *   X         [in]  T x D fields, FP32, row-major with row stride ldx floats;
  *                   16-byte aligned, ldx >= D, ldx % 4 == 0.
@@ -207,8 +208,10 @@ const char* traknn_status_string(int status);
  * When enabled, traknn_knn records HIP events on its stream between its
  * stages; traknn_stage_times then waits for the last event and returns the
  * elapsed milliseconds of each stage in launch order:
- *   0 centre statistics, 1 centre/convert/norms, 2 Gram + distance epilogue,
- *   3 window recurrence + partial top-k, 4 top-k merge.
+ *   0 centre statistics, 1 centre/convert/norms, 2 Gram + distance epilogue
+ *   (in band mode: all passes, each Gram + window + merge),
+ *   3 window recurrence + partial top-k, 4 top-k merge (both about 0 in band
+ *   mode).
  *   enable   [in]  nonzero to record events from the next traknn_knn call on.
  *   ms       [out] host array of at least max_stages doubles.
  *   n_stages [out] number of stages written.
