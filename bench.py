@@ -254,7 +254,7 @@ def main():
     traffic = read_traffic() if hp == "bf16x3" and w.name == "full" else None
     wb = window_bytes(w.T, w.L)
     win_ms = head["stage_ms"]["window_topk"]
-    window_hbm = {"kernel": f"window1_kernel<{w.L}>", "avg_launch_ms": win_ms,
+    window_hbm = {"kernel": f"window1_kernel<{w.L}, 1>", "avg_launch_ms": win_ms,
                   "algorithmic_GBps": wb["algorithmic_bytes"] / (win_ms * 1e-3) / 1e9,
                   "design_GBps": wb["design_bytes"] / (win_ms * 1e-3) / 1e9,
                   "peak_GBps": HBM_PEAK_GBS, **wb}

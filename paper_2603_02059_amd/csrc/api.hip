@@ -44,8 +44,10 @@ bool plan_window(traknn_plan_s* p) {
   const int64_t rows = p->rb ? (p->rb < p->np0 ? p->rb : p->np0) : p->np0;
   const int64_t nrb = (rows + WINDOW1_ROWS - 1) / WINDOW1_ROWS;
   const int64_t nchunks = (p->np0 + WINDOW1_ROWS - 1 + 63) / 64;
-  const size_t base = window1_lds_bytes(L, k, 0);
-  const size_t per_wave = window1_lds_bytes(L, k, 1) - base;
+  // a sweep's passes hold up to WINDOW_LENGTHS_PER_PASS lengths' lists
+  const int G = p->NL > 1 ? WINDOW_LENGTHS_PER_PASS : 1;
+  const size_t base = window1_lds_bytes(L, G, k, 0);
+  const size_t per_wave = window1_lds_bytes(L, G, k, 1) - base;
   if (base + per_wave > MAX_WIN_LDS) return false;
   int64_t W = (WIN_TARGET_UNITS + nrb - 1) / nrb;
   const int64_t wmax = (int64_t)((MAX_WIN_LDS - base) / per_wave);

@@ -159,35 +159,54 @@ __device__ __forceinline__ void seed_row(double d, int c, bool valid, int k, dou
 // afterwards, which is exact because every row of a group is a different row.
 // Chunks wholly inside the row range and clear of the exclusion zone (all but
 // a few per row block) skip the per-lane validity tests.
-template <int L>
+//
+// G consecutive lengths L .. L + G - 1 share one pass over S (a multi-length
+// sweep pairs them): each lane keeps one running sum per length, every length
+// has its own lists, bounds and exclusion zone, and the values of a chunk are
+// read once for all of them. Each length's sums are started and slid exactly
+// as in a pass of its own, so the results do not depend on G.
+template <int L, int G>
 __global__ __launch_bounds__(1024) void window1_kernel(
     const float* __restrict__ S, int64_t ldS, int T, int s0, int s_end, int row_lo,
-    int row_hi, int k, int W, int64_t split_stride, double* __restrict__ part_d,
-    int32_t* __restrict__ part_i) {
+    int row_cap, int k, int W, int64_t split_stride, int64_t len_rows,
+    double* __restrict__ part_d, int32_t* __restrict__ part_i) {
   constexpr int R = W1_ROWS;
   constexpr int U = W1_GROUP;
-  constexpr int M = R + L - 1;
+  constexpr int LG = L + G - 1;  // longest length of the pass
+  constexpr int M = R + LG - 1;  // rows of values per chunk
   extern __shared__ __attribute__((aligned(16))) char smem[];
   const int lane = threadIdx.x & 63;
   const int split = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  unsigned long long* shb = (unsigned long long*)smem;  // [R] bits of the shared bound
-  char* mine = smem + R * sizeof(unsigned long long) +
-               (size_t)split * (W1_VALS_BYTES(M + U) + (size_t)R * k * 12);
+  unsigned long long* shb = (unsigned long long*)smem;  // [G][R] bits of the shared bounds
+  char* mine = smem + G * R * sizeof(unsigned long long) +
+               (size_t)split * (W1_VALS_BYTES(M + U) + (size_t)G * R * k * 12);
   float* vl = (float*)mine;  // [M + U][64]: M rows of values, U rows of padding
-  double* ld = (double*)(mine + W1_VALS_BYTES(M + U));  // [R][k]
-  int* li = (int*)(ld + (size_t)R * k);                   // [R][k]
-  if (threadIdx.x < R) shb[threadIdx.x] = (unsigned long long)__double_as_longlong(__builtin_huge_val());
+  double* ld = (double*)(mine + W1_VALS_BYTES(M + U));  // [G][R][k]
+  int* li = (int*)(ld + (size_t)G * R * k);               // [G][R][k]
+  if (threadIdx.x < G * R)
+    shb[threadIdx.x] = (unsigned long long)__double_as_longlong(__builtin_huge_val());
   __syncthreads();  // the only workgroup barrier: the waves' trip counts differ
 
-  const int npL = T - L + 1;  // candidate trajectories (columns)
   const int r0 = row_lo + (int)blockIdx.x * R;
-  const int nrows = row_hi - r0 < R ? row_hi - r0 : R;  // rows of this block
+  int npl[G];    // candidate trajectories (columns) of each length
+  int nrows[G];  // rows of this block that exist for each length
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    npl[g] = T - (L + g) + 1;
+    const int hi = row_cap < npl[g] ? row_cap : npl[g];
+    nrows[g] = hi - r0 < R ? (hi - r0 > 0 ? hi - r0 : 0) : R;
+  }
   const int64_t dlo = -(int64_t)(r0 + R - 1);
-  const int64_t NC = ((int64_t)npL + R - 1 + 63) / 64;
+  const int64_t NC = ((int64_t)npl[0] + R - 1 + 63) / 64;
   const int64_t cb = (int64_t)split * NC / W, ce = (int64_t)(split + 1) * NC / W;
 
-  double thr_d = __builtin_huge_val();  // lane q: own k-th of row r0 + q
-  int thr_i = INT_MAX;
+  double thr_d[G];  // lane q: own k-th of row r0 + q, per length
+  int thr_i[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    thr_d[g] = __builtin_huge_val();
+    thr_i[g] = INT_MAX;
+  }
 
   // Values of diagonal delta at rows r0 + m (one 256-byte segment per row
   // for the wave), zero outside the matrix. The pointer walks down the rows
@@ -222,27 +241,32 @@ __global__ __launch_bounds__(1024) void window1_kernel(
       }
     }
   };
-  // after the row's own list changed: lower the shared bound to its k-th
-  auto publish = [&](int s) __attribute__((always_inline)) {
-    if (lane == s && thr_d != __builtin_huge_val())
-      atomicMin(&shb[s], (unsigned long long)__double_as_longlong(thr_d));
+  // after a row's own list changed: lower its shared bound to the list's k-th
+  auto publish = [&](int g, int s) __attribute__((always_inline)) {
+    if (lane == s && thr_d[g] != __builtin_huge_val())
+      atomicMin(&shb[g * R + s], (unsigned long long)__double_as_longlong(thr_d[g]));
   };
 
   // First chunk of the range: the lists start empty, so each row's list is
   // seeded with a sort of its first 64 candidates.
   auto seed_chunk = [&](int64_t c) __attribute__((always_inline)) {
     const int delta = (int)(dlo + 64 * c) + lane;
-    const bool okd = (delta >= L) | (delta <= -L);
-    double D = 0.0;
 #pragma unroll
-    for (int l = 0; l < L; ++l) D += (double)vl[l * 64 + lane];
+    for (int g = 0; g < G; ++g) {
+      const int Lg = L + g;
+      const bool okd = (delta >= Lg) | (delta <= -Lg);
+      double D = 0.0;
+#pragma unroll
+      for (int l = 0; l < L + g; ++l) D += (double)vl[l * 64 + lane];
 #pragma unroll 1
-    for (int s = 0; s < nrows; ++s) {
-      const int col = r0 + s + delta;
-      const bool valid = okd & ((unsigned)col < (unsigned)npL);
-      seed_row(D, col, valid, k, ld + s * k, li + s * k, lane, s, thr_d, thr_i);
-      publish(s);
-      D = (D - (double)vl[s * 64 + lane]) + (double)vl[(s + L) * 64 + lane];
+      for (int s = 0; s < nrows[g]; ++s) {
+        const int col = r0 + s + delta;
+        const bool valid = okd & ((unsigned)col < (unsigned)npl[g]);
+        seed_row(D, col, valid, k, ld + (g * R + s) * k, li + (g * R + s) * k, lane, s,
+                 thr_d[g], thr_i[g]);
+        publish(g, s);
+        D = (D - (double)vl[s * 64 + lane]) + (double)vl[(s + Lg) * 64 + lane];
+      }
     }
   };
 
@@ -251,43 +275,59 @@ __global__ __launch_bounds__(1024) void window1_kernel(
   auto scan_chunk = [&](int64_t c, auto edge_c) __attribute__((always_inline)) {
     constexpr bool EDGE = decltype(edge_c)::value;
     const int delta = (int)(dlo + 64 * c) + lane;
-    const bool okd = (delta >= L) | (delta <= -L);
-    double D = 0.0;
+    bool okd[G];
+    double D[G];
 #pragma unroll
-    for (int l = 0; l < L; ++l) D += (double)vl[l * 64 + lane];
+    for (int g = 0; g < G; ++g) {
+      okd[g] = (delta >= L + g) | (delta <= -(L + g));
+      D[g] = 0.0;
+#pragma unroll
+      for (int l = 0; l < L + g; ++l) D[g] += (double)vl[l * 64 + lane];
+    }
 #pragma unroll 1
-    for (int g = 0; g < R; g += U) {
-      float w[U + L];  // rows g .. g+U+L-1
+    for (int gr = 0; gr < R; gr += U) {
+      float w[U + LG];  // rows gr .. gr+U+LG-1
 #pragma unroll
-      for (int j = 0; j < U + L; ++j) w[j] = vl[(g + j) * 64 + lane];
-      // bound per row (lane q < R): own k-th or the shared bound, the smaller
-      const double sh = __longlong_as_double(
-          (long long)__atomic_load_n(&shb[lane & (R - 1)], __ATOMIC_RELAXED));
-      const double bound = __builtin_fmin(thr_d, sh);
-      double Dj[U];
-      uint64_t m[U];
+      for (int j = 0; j < U + LG; ++j) w[j] = vl[(gr + j) * 64 + lane];
+      // bound per row (lane q < R) and length: own k-th or the shared bound,
+      // the smaller
+      double bound[G];
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const double sh = __longlong_as_double(
+            (long long)__atomic_load_n(&shb[g * R + (lane & (R - 1))], __ATOMIC_RELAXED));
+        bound[g] = __builtin_fmin(thr_d[g], sh);
+      }
+      double Dj[G][U];
+      uint64_t m[G][U];
       uint64_t any = 0;
 #pragma unroll
       for (int j = 0; j < U; ++j) {
-        const int s = g + j;
-        Dj[j] = D;
-        bool pass = D <= readlane_d(bound, s);
-        if constexpr (EDGE) {
-          const int col = r0 + s + delta;
-          pass = pass & okd & ((unsigned)col < (unsigned)npL) & (s < nrows);
+        const int s = gr + j;
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+          Dj[g][j] = D[g];
+          bool pass = D[g] <= readlane_d(bound[g], s);
+          if constexpr (EDGE) {
+            const int col = r0 + s + delta;
+            pass = pass & okd[g] & ((unsigned)col < (unsigned)npl[g]) & (s < nrows[g]);
+          }
+          m[g][j] = __ballot(pass);
+          any |= m[g][j];
+          if (j + 1 < U || gr + U < R) D[g] = (D[g] - (double)w[j]) + (double)w[j + L + g];
         }
-        m[j] = __ballot(pass);
-        any |= m[j];
-        if (j + 1 < U || g + U < R) D = (D - (double)w[j]) + (double)w[j + L];
       }
       if (any) {
 #pragma unroll
         for (int j = 0; j < U; ++j) {
-          if (m[j]) {
-            const int s = g + j;
-            insert_seq(m[j], Dj[j], r0 + s + delta, k, ld + s * k, li + s * k, lane, s,
-                       thr_d, thr_i);
-            publish(s);
+#pragma unroll
+          for (int g = 0; g < G; ++g) {
+            if (m[g][j]) {
+              const int s = gr + j;
+              insert_seq(m[g][j], Dj[g][j], r0 + s + delta, k, ld + (g * R + s) * k,
+                         li + (g * R + s) * k, lane, s, thr_d[g], thr_i[g]);
+              publish(g, s);
+            }
           }
         }
       }
@@ -295,7 +335,9 @@ __global__ __launch_bounds__(1024) void window1_kernel(
   };
 
   if (cb < ce) load(cb);
-  const bool full = nrows == R;
+  // interior chunks: every row exists for every length, and the columns and
+  // the exclusion zone of the longest length (the strictest) are clear
+  const bool full = nrows[G - 1] == R;
   for (int64_t c = cb; c < ce; ++c) {
     // park this chunk's values in this wave's LDS rows (LDS accesses of a
     // wave execute in order), then start fetching the next chunk
@@ -305,8 +347,8 @@ __global__ __launch_bounds__(1024) void window1_kernel(
     __builtin_amdgcn_wave_barrier();
     if (c + 1 < ce) load(c + 1);
     const int64_t dc = dlo + 64 * c;
-    const bool interior = full & ((dc >= L) | (dc + 63 <= -L)) & (r0 + dc >= 0) &
-                          (r0 + R - 1 + dc + 63 < npL);
+    const bool interior = full & ((dc >= LG) | (dc + 63 <= -LG)) & (r0 + dc >= 0) &
+                          (r0 + R - 1 + dc + 63 < npl[G - 1]);
     if (c == cb)
       seed_chunk(c);
     else if (interior)
@@ -314,27 +356,32 @@ __global__ __launch_bounds__(1024) void window1_kernel(
     else
       scan_chunk(c, std::true_type{});
   }
-  // partial lists: part[(split * split_stride + row - row_lo) * k + q]; a
-  // range with no chunk leaves its lists empty
-  for (int s = 0; s < nrows; ++s) {
-    const int row = r0 - row_lo + s;
-    if (lane < k) {
-      const int64_t o = ((int64_t)split * split_stride + row) * k + lane;
-      part_d[o] = cb < ce ? ld[s * k + lane] : __builtin_huge_val();
-      part_i[o] = cb < ce ? li[s * k + lane] : INT_MAX;
+  // partial lists: part[(split * split_stride + g * len_rows + row - row_lo) * k
+  // + q] for length L + g; a range with no chunk leaves its lists empty
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    for (int s = 0; s < nrows[g]; ++s) {
+      const int64_t row = (int64_t)g * len_rows + (r0 - row_lo + s);
+      if (lane < k) {
+        const int64_t o = ((int64_t)split * split_stride + row) * k + lane;
+        part_d[o] = cb < ce ? ld[(g * R + s) * k + lane] : __builtin_huge_val();
+        part_i[o] = cb < ce ? li[(g * R + s) * k + lane] : INT_MAX;
+      }
     }
   }
 }
 
-// Row blocks of length L: ceil((row_hi - row_lo) / W1_ROWS) workgroups of W waves.
-template <int L>
+// Row blocks of lengths L .. L + G - 1: ceil((rows of length L) / W1_ROWS)
+// workgroups of W waves.
+template <int L, int G>
 hipError_t launch_win1(const float* S, int64_t ldS, int T, int s0, int s_end, int row_lo,
-                       int row_hi, int k, int W, int64_t split_stride, double* pd,
-                       int32_t* pi, hipStream_t s) {
-  const size_t lds = window1_lds_bytes(L, k, W);
-  const unsigned blocks = (unsigned)((row_hi - row_lo + W1_ROWS - 1) / W1_ROWS);
-  hipLaunchKernelGGL((window1_kernel<L>), dim3(blocks), dim3(64 * W), lds, s, S, ldS, T,
-                     s0, s_end, row_lo, row_hi, k, W, split_stride, pd, pi);
+                       int row_cap, int k, int W, int64_t split_stride, int64_t len_rows,
+                       double* pd, int32_t* pi, hipStream_t s) {
+  const size_t lds = window1_lds_bytes(L + G - 1, G, k, W);
+  const int hi = row_cap < T - L + 1 ? row_cap : T - L + 1;
+  const unsigned blocks = (unsigned)((hi - row_lo + W1_ROWS - 1) / W1_ROWS);
+  hipLaunchKernelGGL((window1_kernel<L, G>), dim3(blocks), dim3(64 * W), lds, s, S, ldS, T,
+                     s0, s_end, row_lo, row_cap, k, W, split_stride, len_rows, pd, pi);
   return hipGetLastError();
 }
 
@@ -444,9 +491,9 @@ __global__ __launch_bounds__(256) void local_dim_kernel(
 
 }  // namespace
 
-size_t window1_lds_bytes(int L, int k, int W) {
-  return (size_t)W1_ROWS * sizeof(unsigned long long) +
-         (size_t)W * (W1_VALS_BYTES(W1_ROWS + L - 1 + W1_GROUP) + (size_t)W1_ROWS * k * 12);
+size_t window1_lds_bytes(int L, int G, int k, int W) {
+  return (size_t)G * W1_ROWS * sizeof(unsigned long long) +
+         (size_t)W * (W1_VALS_BYTES(W1_ROWS + L - 1 + W1_GROUP) + (size_t)G * W1_ROWS * k * 12);
 }
 
 hipError_t launch_window_topk(const float* S, int64_t ldS, int64_t T, int L_min,
@@ -463,41 +510,76 @@ hipError_t launch_window_band(const float* S, int64_t ldS, int64_t T, int L_min,
   const int NL = L_max - L_min + 1;
   // partial lists: [split][length][row - t0][k]
   const int64_t split_stride = (int64_t)NL * nt;
-  for (int L = L_min; L <= L_max; ++L) {
+  // a sweep runs its lengths WINDOW_LENGTHS_PER_PASS at a time (the last pass
+  // takes what is left), a single length on its own
+  for (int L = L_min; L <= L_max;) {
+    const int G = L_max - L + 1 >= WINDOW_LENGTHS_PER_PASS ? WINDOW_LENGTHS_PER_PASS : 1;
     const int64_t off = (int64_t)(L - L_min) * nt * k;
     double* pd = part_d + off;
     int32_t* pi = part_i + off;
-    // rows of this length in [t0, t0 + nt): those with t <= T - L
+    // rows of length L in [t0, t0 + nt): those with t <= T - L (longer lengths
+    // of the pass have fewer; none at all means the merge marks them absent)
     const int64_t hi = t0 + nt < T - L + 1 ? t0 + nt : T - L + 1;
-    if (hi <= t0) continue;  // none (the merge marks them non-existent)
-    const int a = (int)s0, b = (int)s_end, lo = (int)t0, h = (int)hi;
-    hipError_t e;
-    switch (L) {
-#define TRAKNN_WIN1_CASE(n) \
-  case n:                   \
-    e = launch_win1<n>(S, ldS, (int)T, a, b, lo, h, k, splits, split_stride, pd, pi, s); \
+    if (hi > t0) {
+      const int a = (int)s0, b = (int)s_end, lo = (int)t0, cap = (int)(t0 + nt);
+      hipError_t e;
+      if (G == 2) {
+        switch (L) {
+#define TRAKNN_WIN2_CASE(n)                                                                  \
+  case n:                                                                                    \
+    e = launch_win1<n, 2>(S, ldS, (int)T, a, b, lo, cap, k, splits, split_stride, nt, pd, pi, \
+                          s);                                                                \
     break;
-      TRAKNN_WIN1_CASE(1)
-      TRAKNN_WIN1_CASE(2)
-      TRAKNN_WIN1_CASE(3)
-      TRAKNN_WIN1_CASE(4)
-      TRAKNN_WIN1_CASE(5)
-      TRAKNN_WIN1_CASE(6)
-      TRAKNN_WIN1_CASE(7)
-      TRAKNN_WIN1_CASE(8)
-      TRAKNN_WIN1_CASE(9)
-      TRAKNN_WIN1_CASE(10)
-      TRAKNN_WIN1_CASE(11)
-      TRAKNN_WIN1_CASE(12)
-      TRAKNN_WIN1_CASE(13)
-      TRAKNN_WIN1_CASE(14)
-      TRAKNN_WIN1_CASE(15)
-      TRAKNN_WIN1_CASE(16)
+          TRAKNN_WIN2_CASE(1)
+          TRAKNN_WIN2_CASE(2)
+          TRAKNN_WIN2_CASE(3)
+          TRAKNN_WIN2_CASE(4)
+          TRAKNN_WIN2_CASE(5)
+          TRAKNN_WIN2_CASE(6)
+          TRAKNN_WIN2_CASE(7)
+          TRAKNN_WIN2_CASE(8)
+          TRAKNN_WIN2_CASE(9)
+          TRAKNN_WIN2_CASE(10)
+          TRAKNN_WIN2_CASE(11)
+          TRAKNN_WIN2_CASE(12)
+          TRAKNN_WIN2_CASE(13)
+          TRAKNN_WIN2_CASE(14)
+          TRAKNN_WIN2_CASE(15)
+#undef TRAKNN_WIN2_CASE
+          default:
+            return hipErrorInvalidValue;
+        }
+      } else {
+        switch (L) {
+#define TRAKNN_WIN1_CASE(n)                                                                  \
+  case n:                                                                                    \
+    e = launch_win1<n, 1>(S, ldS, (int)T, a, b, lo, cap, k, splits, split_stride, nt, pd, pi, \
+                          s);                                                                \
+    break;
+          TRAKNN_WIN1_CASE(1)
+          TRAKNN_WIN1_CASE(2)
+          TRAKNN_WIN1_CASE(3)
+          TRAKNN_WIN1_CASE(4)
+          TRAKNN_WIN1_CASE(5)
+          TRAKNN_WIN1_CASE(6)
+          TRAKNN_WIN1_CASE(7)
+          TRAKNN_WIN1_CASE(8)
+          TRAKNN_WIN1_CASE(9)
+          TRAKNN_WIN1_CASE(10)
+          TRAKNN_WIN1_CASE(11)
+          TRAKNN_WIN1_CASE(12)
+          TRAKNN_WIN1_CASE(13)
+          TRAKNN_WIN1_CASE(14)
+          TRAKNN_WIN1_CASE(15)
+          TRAKNN_WIN1_CASE(16)
 #undef TRAKNN_WIN1_CASE
-      default:
-        return hipErrorInvalidValue;
+          default:
+            return hipErrorInvalidValue;
+        }
+      }
+      if (e != hipSuccess) return e;
     }
-    if (e != hipSuccess) return e;
+    L += G;
   }
   return hipSuccess;
 }
