@@ -173,3 +173,18 @@ def test_backward_needs_single_length():
         assert e.value.code == -2
     finally:
         tk.traknn_plan_destroy(h)
+
+
+def test_plain_c_client(tmp_path):
+    """The ABI is usable from C99 with the header alone: build a small C client
+    against the library and run it (plans and validation only, no GPU)."""
+    src = os.path.join(ROOT, "tests", "c_abi_check.c")
+    exe = str(tmp_path / "c_abi_check")
+    libdir = os.path.dirname(tk.LIB_PATH)
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Wextra", "-Werror",
+                    "-I", os.path.join(ROOT, "include"), src, "-L", libdir, "-ltraknn",
+                    f"-Wl,-rpath,{libdir}", "-Wl,-rpath-link,/opt/rocm/lib", "-o", exe],
+                   check=True, capture_output=True, text=True)
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 0, r.stderr
+    assert "c abi ok" in r.stdout

@@ -312,3 +312,34 @@ def test_local_dim_every_k():
     assert np.all(err <= _dim_tol(ref[:, 1:], 1e-5)), float(err.max())
     _say(f"  mean local dimension k'=20,30,40: "
          f"{[round(float(np.mean(ld_h[:, q - 1])), 2) for q in (20, 30, 40)]}")
+
+
+@pytest.mark.parametrize("L,k,D", [(1, 1, 1), (2, 2, 3), (5, 10, 64), (16, 1, 7), (16, 64, 33),
+                                   (3, 5, 1000)])
+def test_smallest_legal_series(L, k, D):
+    """T at the smallest value the plan accepts (n' = k + 2L - 1: every row has
+    exactly k candidates or more, the middle row exactly k), one block, one
+    chunk, every lane at an edge; lists against the oracle exactly (every
+    candidate set is forced in the middle row) and the scores within the
+    workload tolerance plus the norm-relative floor."""
+    T = k + 3 * L - 2
+    _say(f"[gpu] smallest legal series T={T} L={L} k={k} D={D}")
+    rng = np.random.default_rng(L * 100 + k)
+    Xn = (rng.standard_normal((T, D)) * 1000.0 + 101300.0).astype(np.float32)
+    tk = _tk()
+    with pytest.raises(tk.TraknnError):
+        tk.Plan(T - 1, D, L, L, k, "bf16x3")
+    for prec in ("fp32", "bf16x3"):
+        idx, dist, s = _run(Xn, L, k, prec)
+        n = T - L + 1
+        ref = oracle.knn(Xn, L, k)
+        Dm = oracle.traj_dist(Xn, L)
+        stats = check_rows(Xn, L, k, np.arange(n), idx[0], dist[0], s[0], precision_tol(prec),
+                           ref=(ref[0], ref[1], ref[2], ref[3], Dm),
+                           norm_tol=gram_norm_tol(prec, D))
+        _say(f"  {prec}: {stats}")
+        # the middle row has exactly k candidates: its set is forced
+        mid = (n - 1) // 2
+        cands = [j for j in range(n) if abs(j - mid) >= L]
+        if len(cands) == k:
+            assert sorted(idx[0][mid].tolist()) == cands
