@@ -17,15 +17,15 @@
 // insertions shift a sorted list held one entry per lane.
 //
 // In band mode (row-batched streaming) S holds only rows s0 .. s_end - 1 of the
-// matrix, and a launch covers the trajectory rows row_lo .. row_hi - 1 whose
+// matrix, and a launch covers the trajectory rows row_lo .. row_cap - 1 whose
 // windows lie inside them; its partial lists are indexed from row_lo.
 //
-// A multi-length request (L = L_min .. L_max) runs the kernel once per length
-// on the same distance matrix, each with its own lists and exclusion zone
-// |i - j| >= L; the merge kernel then combines, per length and row, the W
-// partial lists of the row's column ranges into the final k in (distance,
-// index) order. The result does not depend on the order in which the waves
-// run.
+// A multi-length request (L = L_min .. L_max) runs the kernel once per pair of
+// lengths on the same distance matrix, each length with its own running sums,
+// lists and exclusion zone |i - j| >= L; the merge kernel then combines, per
+// length and row, the W partial lists of the row's column ranges into the
+// final k in (distance, index) order. The result does not depend on the order
+// in which the waves run, nor on how the lengths are grouped into passes.
 #include <cfloat>
 #include <climits>
 #include <type_traits>
