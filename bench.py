@@ -10,6 +10,10 @@ Metric: trajectory pairs per second, n'^2 / step time with n' = T - L + 1.
 The headline path is the split BF16x3 Gram; the plain FP32 and single-pass
 FP16 paths are timed beside it. One JSON line goes to stdout; progress to
 stderr.
+
+``--scaling`` instead times the shapes of the paper's scaling study (Section
+4, Fig. 1: defaults T = 27000 random fields of 180 x 280, d = 1, k = 1, then
+one parameter swept at a time) and prints one JSON line per shape.
 """
 from __future__ import annotations
 
@@ -147,6 +151,44 @@ def cpu_baseline(Xn, w, budget_s, gidx, gdist, gscore):
     }, par
 
 
+def scaling(tk, torch, steps, warmup):
+    """Time the scaling study's shapes (Section 4, Fig. 1) on random fields
+    (the paper evaluates on synthetic random data): the defaults, then the
+    grid side h (w = h), the number of fields T, the length d and k swept one
+    at a time. BF16x3; the defaults also in FP32."""
+    base = {"T": 27000, "h": 180, "w": 280, "d": 1, "k": 1}
+    shapes = [dict(base, prec="bf16x3"), dict(base, prec="fp32")]
+    shapes += [dict(base, h=h, w=h, prec="bf16x3") for h in (45, 90, 135, 225)]
+    shapes += [dict(base, T=T, prec="bf16x3") for T in (5000, 10000, 20000, 40000)]
+    shapes += [dict(base, d=d, prec="bf16x3") for d in (2, 5, 10, 15)]
+    shapes += [dict(base, k=k, prec="bf16x3") for k in (5, 10, 20, 50)]
+    gen = torch.Generator(device="cuda")
+    for sh in shapes:
+        T, D, L, k = sh["T"], sh["h"] * sh["w"], sh["d"], sh["k"]
+        gen.manual_seed(T * 7 + D)
+        X = torch.randn((T, D), generator=gen, device="cuda", dtype=torch.float32)
+        p = tk.Plan(T, D, L, L, k, sh["prec"])
+        idx, dist = p.empty_outputs()
+        scores = torch.empty((1, p.np0), dtype=torch.float64, device="cuda")
+        for _ in range(warmup):
+            p.knn(X, idx, dist)
+            p.score(dist, scores)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            p.knn(X, idx, dist)
+            p.score(dist, scores)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / steps
+        n = T - L + 1
+        line = {"shape": sh, "D": D, "ms_per_call": ms, "pairs_per_s": n * n / (ms * 1e-3),
+                "workspace_GiB": p.ws_bytes / 2 ** 30}
+        print(json.dumps(line), flush=True)
+        p.close()
+        del X, idx, dist, scores
+        torch.cuda.empty_cache()
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -158,6 +200,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0,
                     help="seconds of oracle time for the CPU baseline (0 = skip)")
     ap.add_argument("--only", default=None, help="time one precision only")
+    ap.add_argument("--scaling", action="store_true",
+                    help="time the paper's scaling-study shapes instead (one JSON line each)")
     ap.add_argument("--band-rows", type=int, default=4088,
                     help="also time band mode (row-batched streaming) with passes of "
                          "this many rows, BF16x3 (0 = skip)")
@@ -174,6 +218,10 @@ def main():
 
     from paper_2603_02059_amd import synth
     from paper_2603_02059_amd import traknn as tk
+
+    if args.scaling:
+        scaling(tk, torch, max(1, min(args.steps, 5)), max(1, args.warmup))
+        return
 
     w = synth.WORKLOADS[args.workload]
     t0 = time.perf_counter()
