@@ -8,9 +8,9 @@
 // built as a CSR: integer counting with atomics, a scan, an atomic fill and a
 // per-bucket sort by t, so the reverse lists -- and hence every floating-point
 // sum -- come out in the same order on every run. Each output row is then
-// gathered by one workgroup in FP64 (field differences of FP32 inputs are
-// exact in FP64) and rounded once to FP32; rows that no term touches keep the
-// zeros of a fill pass and are not gathered. No distance value is needed: the
+// gathered in FP64 (field differences of FP32 inputs are exact in FP64) and
+// rounded once to FP32; rows that no term touches are written as zeros by the
+// same kernel. No distance value is needed: the
 // derivative of a squared distance is the field difference itself.
 #include "internal.h"
 
@@ -91,10 +91,13 @@ __global__ __launch_bounds__(256) void rev_sort_kernel(const int32_t* __restrict
   }
 }
 
-constexpr int GCOLS = 32;  // columns per thread per pass (8192 per pass)
+// Columns per thread: a workgroup gathers one output row over 256 * GCOLS
+// columns, and a second grid dimension covers the rest of the row, so a row's
+// terms are gathered by several workgroups at once (the gather is latency
+// bound: each term is one dependent source-row read).
+constexpr int GCOLS = 4;
 
-// Does output row a receive any term? (Rows that do not keep the zeros the
-// fill kernel wrote.)
+// Does output row a receive any term?
 __device__ __forceinline__ bool row_has_terms(int a, int np, int L, const double* w,
                                               const int32_t* ptr) {
   for (int m = 0; m < L; ++m) {
@@ -104,18 +107,6 @@ __device__ __forceinline__ bool row_has_terms(int a, int np, int L, const double
   return false;
 }
 
-// Zero every row of the gradient: block b clears 1024 floats of row
-// b / per_row.
-__global__ __launch_bounds__(256) void zero_rows_kernel(float* __restrict__ g, int64_t ldg,
-                                                        int64_t D, int64_t per_row) {
-  const int64_t row = blockIdx.x / per_row;
-  const int64_t p0 = (blockIdx.x % per_row) * 1024 + threadIdx.x;
-  float* r = g + row * ldg;
-#pragma unroll
-  for (int u = 0; u < 4; ++u)
-    if (p0 + 256 * u < D) r[p0 + 256 * u] = 0.f;
-}
-
 __global__ __launch_bounds__(256) void grad_rows_kernel(
     const float* __restrict__ X, int64_t ldx, int T, int64_t D, int L, int k,
     const int32_t* __restrict__ idx, const double* __restrict__ w,
@@ -123,10 +114,19 @@ __global__ __launch_bounds__(256) void grad_rows_kernel(
     float* __restrict__ g, int64_t ldg) {
   const int a = blockIdx.x;
   const int np = T - L + 1;
-  if (!row_has_terms(a, np, L, w, ptr)) return;  // stays zero
+  const int64_t c0 = (int64_t)blockIdx.y * 256 * GCOLS;
+  float* ga = g + (int64_t)a * ldg;
+  if (!row_has_terms(a, np, L, w, ptr)) {  // untouched row: zeros
+#pragma unroll
+    for (int e = 0; e < GCOLS; ++e) {
+      const int64_t p = c0 + threadIdx.x + 256 * e;
+      if (p < D) ga[p] = 0.f;
+    }
+    return;
+  }
   const double invk = 1.0 / (double)k;
   const float* xa = X + (int64_t)a * ldx;
-  for (int64_t c0 = 0; c0 < D; c0 += 256 * GCOLS) {
+  {
     double acc[GCOLS];
     double xav[GCOLS];
 #pragma unroll
@@ -168,7 +168,6 @@ __global__ __launch_bounds__(256) void grad_rows_kernel(
         }
       }
     }
-    float* ga = g + (int64_t)a * ldg;
 #pragma unroll
     for (int e = 0; e < GCOLS; ++e) {
       const int64_t p = c0 + threadIdx.x + 256 * e;
@@ -194,10 +193,8 @@ hipError_t launch_backward(const float* X, int64_t ldx, int64_t T, int64_t D,
   hipLaunchKernelGGL(rev_fill_kernel, dim3(gk), dim3(256), 0, s, idx, w, np, k, ptr,
                      fill, rev);
   hipLaunchKernelGGL(rev_sort_kernel, dim3(gb), dim3(256), 0, s, ptr, np, rev);
-  const int64_t per_row = (D + 1023) / 1024;
-  hipLaunchKernelGGL(zero_rows_kernel, dim3((unsigned)(T * per_row)), dim3(256), 0, s, g, ldg,
-                     D, per_row);
-  hipLaunchKernelGGL(grad_rows_kernel, dim3((unsigned)T), dim3(256), 0, s, X, ldx,
+  const unsigned col_blocks = (unsigned)((D + 256 * GCOLS - 1) / (256 * GCOLS));
+  hipLaunchKernelGGL(grad_rows_kernel, dim3((unsigned)T, col_blocks), dim3(256), 0, s, X, ldx,
                      (int)T, D, L, k, idx, w, ptr, rev, g, ldg);
   return hipGetLastError();
 }
