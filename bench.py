@@ -112,6 +112,36 @@ def time_path(tk, torch, X, w, prec, steps, warmup, row_batch=0):
     return out
 
 
+def time_backward(tk, torch, synth, steps):
+    """The differentiation configuration: T = 10957 daily 64 x 128 fields,
+    L = 5, k = 10, FP32 forward, then the backward of the summed score of the
+    100 rarest trajectories (neighbour sets held fixed)."""
+    w = synth.WORKLOADS["bwd"]
+    Xn, _ = synth.make_workload(w)
+    X = torch.from_numpy(Xn).cuda()
+    p = tk.Plan(w.T, w.D, w.L, w.L, w.k, "fp32")
+    idx, dist = p.knn(X)
+    s = p.score(dist)[0]
+    wts = torch.zeros_like(s)
+    wts[torch.argsort(-s)[:100]] = 1.0
+    g = p.backward(X, idx[0], wts)
+    torch.cuda.synchronize()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    e[0].record()
+    for _ in range(steps):
+        p.knn(X, idx, dist)
+    e[1].record()
+    for _ in range(steps):
+        p.backward(X, idx[0], wts, grad_X=g)
+    e[2].record()
+    torch.cuda.synchronize()
+    out = {"config": f"T={w.T}, D={w.D}, L={w.L}, k={w.k}, FP32, 100 rarest",
+           "forward_ms": e[0].elapsed_time(e[1]) / steps,
+           "backward_ms": e[1].elapsed_time(e[2]) / steps}
+    p.close()
+    return out
+
+
 def cpu_baseline(Xn, w, budget_s, gidx, gdist, gscore):
     """The FP64 oracle on evenly spaced sample rows, timed on the host cores,
     plus the parity of the GPU rows against it."""
@@ -200,6 +230,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0,
                     help="seconds of oracle time for the CPU baseline (0 = skip)")
     ap.add_argument("--only", default=None, help="time one precision only")
+    ap.add_argument("--no-backward", action="store_true",
+                    help="skip the backward timing (T = 10957 configuration)")
     ap.add_argument("--scaling", action="store_true",
                     help="time the paper's scaling-study shapes instead (one JSON line each)")
     ap.add_argument("--band-rows", type=int, default=4088,
@@ -282,6 +314,12 @@ def main():
             band["rows_with_whole_matrix_set"] = float(np.all(a == b, axis=1).mean())
         log(f"[bench] band mode: {band}")
 
+    bwd = None
+    if not args.no_backward and not args.only:
+        log("[bench] timing the backward configuration")
+        bwd = time_backward(tk, torch, synth, max(args.compare_steps, 5))
+        log(f"[bench] backward: {bwd}")
+
     head = results[precs[0]]
     hp = head["prec"]
     gidx = head["idx"].cpu().numpy()
@@ -338,6 +376,7 @@ def main():
                   for p, r in results.items()},
         "window_hbm": window_hbm,
         "band_mode": band,
+        "backward": bwd,
         "parity_sample": par,
         "planted_in_top40": f"{planted_found}/{len(starts)}",
     }
