@@ -1,0 +1,51 @@
+"""Host-side checks of bench.py (no GPU): the multi-GPU refusal, the
+algorithmic work figures its roofline uses, and that every shape it times is
+accepted by the planner."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+from paper_2603_02059_amd import traknn as tk  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
+
+
+def test_gram_flops():
+    # upper triangle with the diagonal: T(T+1)/2 pairs, 2D flop each, x3 for BF16x3
+    assert bench.gram_flops(4, 10, "fp32") == 2 * 10 * 10
+    assert bench.gram_flops(4, 10, "bf16x3") == 3 * 2 * 10 * 10
+    T, D = 27394, 8192
+    assert bench.gram_flops(T, D, "bf16x3") == pytest.approx(1.8443e13, rel=1e-4)
+
+
+def test_window_bytes():
+    wb = bench.window_bytes(100, 5, rows=8)
+    assert wb["algorithmic_bytes"] == 4.0 * 100 * 101 / 2
+    assert wb["design_bytes"] == 4.0 * 100 * 100 * 12 / 8
+
+
+@pytest.mark.parametrize("T,D,L,k,prec,rb", [
+    (27394, 8192, 5, 10, "bf16x3", 0), (27394, 8192, 5, 10, "fp32", 0),
+    (27394, 8192, 5, 10, "fp16", 0), (27394, 8192, 5, 10, "bf16x3", 4088),
+    (10957, 8192, 5, 10, "fp32", 0),
+    (27000, 50400, 1, 1, "bf16x3", 0), (27000, 2025, 1, 1, "bf16x3", 0),
+    (40000, 50400, 1, 1, "bf16x3", 0), (27000, 50400, 15, 1, "bf16x3", 0),
+    (27000, 50400, 1, 50, "bf16x3", 0), (27000, 50625, 1, 1, "bf16x3", 0),
+])
+def test_timed_shapes_plan(T, D, L, k, prec, rb):
+    h, ws = tk.traknn_plan(T, D, L, L, k, prec, rb)
+    tk.traknn_plan_destroy(h)
+    # every timed shape fits one MI355X (288 GiB)
+    assert ws < 288 * 2 ** 30
