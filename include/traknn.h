@@ -13,7 +13,8 @@
  *   s_t      = (1/k) sum_{j in N_t} D_L(t,j)                    (Eq. 3)
  *
  * and the gradient of sum_t w_t s_t with respect to the fields, the neighbour
- * sets held fixed.
+ * sets held fixed; from the same lists, the scores for every k' <= k and the
+ * local intrinsic dimension of every trajectory.
  *
  * Conventions shared by every entry point
  *   - All array pointers are DEVICE pointers (hipMalloc'd or equivalent) owned
@@ -52,7 +53,9 @@ extern "C" {
 #define TRAKNN_ERR_HIP (-4)         /* a HIP runtime call or kernel launch failed */
 
 /* Precision of the Gram contraction (Eq. 4). In every mode the fields are first
- * centred per grid cell in FP64 (distances are translation invariant); squared
+ * shifted per grid cell by an FP64 mean over at most 2048 evenly strided
+ * fields (distances are translation invariant, so any shift is exact; it only
+ * removes the ~1e5 Pa offset before the reduced-precision products); squared
  * norms are FP64 sums over chunks of 512 cells of the represented vectors,
  * which the FP32 Gram accumulators subtract chunk by chunk so that they carry
  * -d/2 rather than the inner product (rounding errors scale with the distance,
