@@ -141,3 +141,14 @@ def test_band_beyond_device_memory():
     stats = check_rows(Xn, L, k, rows, idx[rows], dist[rows], s[rows],
                        precision_tol("bf16x3"), norm_tol=gram_norm_tol("bf16x3", H * W))
     _say(f"  {stats}")
+
+
+def test_band_determinism():
+    """Band mode gives the same lists, distances and scores on every run."""
+    T, D, L, k, rb = 700, 300, 4, 7, 128
+    _say(f"[gpu-band] determinism T={T} D={D} row_batch={rb}")
+    Xn, _ = synth.make_fields(T, 1, D, sigma=2.0, n_events=2, event_len=L, seed=3)
+    a = _run(Xn, L, k, "bf16x3", rb)
+    b = _run(Xn, L, k, "bf16x3", rb)
+    for u, v in zip(a, b):
+        assert np.array_equal(u, v)

@@ -125,9 +125,15 @@ def test_all_lengths_sweep():
         stats = check_rows(Xn, L, w.k, rows, idx[L - 1][rows], dist[L - 1][rows],
                            s[L - 1][rows], precision_tol("bf16x3"))
         _say(f"  L={L}: {stats}")
-    # the sweep and a single-length run agree (same S, different summation order)
-    i5, d5, s5 = _run(Xn, 5, 5, w.k, "bf16x3")
-    np.testing.assert_allclose(s[4, : w.T - 4], s5[0], rtol=1e-12)
+    # the sweep and single-length runs agree bit for bit (same distance
+    # matrix; each length's sums started and slid the same way, whether it
+    # shares a pass with another length or not)
+    for L in (5, 10):
+        iL, dL, sL = _run(Xn, L, L, w.k, "bf16x3")
+        n = w.T - L + 1
+        assert np.array_equal(idx[L - 1, :n], iL[0])
+        assert np.array_equal(dist[L - 1, :n], dL[0])
+        assert np.array_equal(s[L - 1, :n], sL[0])
 
 
 def test_small_grid_full_length():

@@ -135,9 +135,13 @@ def test_multi_length_sweep():
         _say(f"  L={L}: {stats}")
         assert np.all(idx[L - 1, n:] == -1) and np.all(np.isinf(dist[L - 1, n:]))
         assert np.all(np.isnan(s[L - 1, n:]))
-        # one pass over all lengths = separate single-length runs
+        # one pass over all lengths = separate single-length runs, bit for bit:
+        # the same distance matrix, and each length's sums started and slid
+        # the same way whether or not it shares its pass with another length
         i1, d1, s1 = _run(Xn, L, k, "bf16x3")
-        np.testing.assert_allclose(s[L - 1, :n], s1[0], rtol=1e-12)
+        assert np.array_equal(idx[L - 1, :n], i1[0])
+        assert np.array_equal(dist[L - 1, :n], d1[0])
+        assert np.array_equal(s[L - 1, :n], s1[0])
 
 
 def test_sweep_all_lengths_max_k():
