@@ -112,6 +112,32 @@ def time_path(tk, torch, X, w, prec, steps, warmup, row_batch=0):
     return out
 
 
+def time_sweep(tk, torch, X, w, steps, warmup, L_max=10):
+    """The all-lengths configuration: L = 1..L_max in one call on the full
+    workload, BF16x3 (one Gram, the window passes two lengths at a time)."""
+    p = tk.Plan(w.T, w.D, 1, L_max, w.k, "bf16x3")
+    idx, dist = p.empty_outputs()
+    scores = torch.empty((p.NL, p.np0), dtype=torch.float64, device=X.device)
+    for _ in range(warmup):
+        p.knn(X, idx, dist)
+        p.score(dist, scores)
+    torch.cuda.synchronize()
+    p.set_timing(True)
+    st = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        p.knn(X, idx, dist)
+        p.score(dist, scores)
+        st.append(p.stage_times())
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    p.set_timing(False)
+    out = {"lengths": f"1..{L_max}", "ms_per_call": ms,
+           "stage_ms": {k: float(np.mean([s[k] for s in st])) for k in st[0]}}
+    p.close()
+    return out
+
+
 def time_backward(tk, torch, synth, steps):
     """The differentiation configuration: T = 10957 daily 64 x 128 fields,
     L = 5, k = 10, FP32 forward, then the backward of the summed score of the
@@ -314,6 +340,12 @@ def main():
             band["rows_with_whole_matrix_set"] = float(np.all(a == b, axis=1).mean())
         log(f"[bench] band mode: {band}")
 
+    sweep = None
+    if not args.only:
+        log("[bench] timing the all-lengths sweep L=1..10")
+        sweep = time_sweep(tk, torch, X, w, args.compare_steps, args.warmup)
+        log(f"[bench] sweep: {sweep}")
+
     bwd = None
     if not args.no_backward and not args.only:
         log("[bench] timing the backward configuration")
@@ -376,6 +408,7 @@ def main():
                   for p, r in results.items()},
         "window_hbm": window_hbm,
         "band_mode": band,
+        "sweep": sweep,
         "backward": bwd,
         "parity_sample": par,
         "planted_in_top40": f"{planted_found}/{len(starts)}",
