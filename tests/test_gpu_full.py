@@ -257,3 +257,20 @@ def test_local_dim_sweep():
             err = np.abs(got[:, 1:] - ref[:, 1:])
             tol = 2.0 * ref[:, 1:] ** 2 * 1e-5 + 1e-12 * ref[:, 1:]
             assert np.all(err <= tol), float(err.max())
+
+
+def test_paper_scaling_default_shape():
+    """The default shape of the paper's scaling study (Section 4): T = 27000
+    random fields of 180 x 280 (D = 50400), d = 1, k = 1 (the matrix-profile
+    case), BF16x3. Every row's list is valid; sampled rows match the oracle."""
+    T, H, W, L, k = 27000, 180, 280, 1, 1
+    _say(f"[gpu-full] paper scaling default T={T} D={H * W} L={L} k={k}")
+    rng = np.random.default_rng(2603)
+    Xn = rng.standard_normal((T, H * W), dtype=np.float32)
+    idx, dist, s = _run(Xn, L, L, k, "bf16x3")
+    idx, dist, s = idx[0], dist[0], s[0]
+    _check_all_rows(idx, dist, s, L, k)
+    rows = np.unique(np.concatenate([np.linspace(0, T - 1, 14).astype(np.int64), [1, T - 2]]))
+    stats = check_rows(Xn, L, k, rows, idx[rows], dist[rows], s[rows], precision_tol("bf16x3"))
+    _say(f"  {stats}")
+    del Xn
