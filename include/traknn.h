@@ -64,11 +64,13 @@ extern "C" {
  *   TRAKNN_FP32   : centred fields rounded to FP32, FP32 MFMA (32x32x2).
  *   TRAKNN_BF16X3 : centred fields split hi = bf16(x), lo = bf16(x - hi);
  *                   G = hi.hi' + hi.lo' + lo.hi' on BF16 MFMA (32x32x16) with FP32
- *                   accumulation (the lo.lo' term is dropped). The accumulation
- *                   error grows like sqrt(3 D / 16) * 2^-24 relative to the
- *                   distance: about 2e-6 at D = 8192 and 6e-6 at D = 50400, so
- *                   for grids beyond about 1.5e5 cells the FP32 mode is the one
- *                   that stays within 1e-5.
+ *                   accumulation (the lo.lo' term is dropped).
+ * In every mode the FP32 accumulator is rounded once per MFMA, n times per
+ * distance (n = 3 D / 16 for BF16X3, D / 2 for FP32, D / 16 for FP16), so the
+ * accumulation error grows like sqrt(n) * 2^-24 relative to the distance. For
+ * BF16X3 the largest errors observed are 2e-6 at D = 8192 and 6e-6 at
+ * D = 50400; by that trend 1e-5 is reached near D = 1.5e5 (near D = 6e4 for
+ * FP32, which rounds 2.7x as often).
  *   TRAKNN_FP16   : centred fields rounded to FP16, one FP16 MFMA pass (32x32x16).
  *                   Requires |x - mean| < 65504 in every cell. */
 #define TRAKNN_FP32 0
