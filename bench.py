@@ -218,6 +218,10 @@ def scaling(tk, torch, steps, warmup):
     shapes += [dict(base, T=T, prec="bf16x3") for T in (5000, 10000, 20000, 40000)]
     shapes += [dict(base, d=d, prec="bf16x3") for d in (2, 5, 10, 15)]
     shapes += [dict(base, k=k, prec="bf16x3") for k in (5, 10, 20, 50)]
+    # the case study's scale (Section 5): 75 years of daily 181 x 281 fields,
+    # d = 5, k = 10
+    shapes += [{"T": 27394, "h": 181, "w": 281, "d": 5, "k": 10, "prec": p}
+               for p in ("bf16x3", "fp32")]
     gen = torch.Generator(device="cuda")
     for sh in shapes:
         T, D, L, k = sh["T"], sh["h"] * sh["w"], sh["d"], sh["k"]
