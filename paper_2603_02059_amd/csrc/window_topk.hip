@@ -26,9 +26,11 @@
 // length and row, the W partial lists of the row's column ranges into the
 // final k in (distance, index) order. The result does not depend on the order
 // in which the waves run, nor on how the lengths are grouped into passes.
+#include <array>
 #include <cfloat>
 #include <climits>
 #include <type_traits>
+#include <utility>
 
 #include "internal.h"
 
@@ -491,6 +493,17 @@ __global__ __launch_bounds__(256) void local_dim_kernel(
 
 }  // namespace
 
+// Launchers of every compiled (L, G): kWin1[L - 1] for L = 1..TRAKNN_MAX_L on
+// its own, kWin2[L - 1] for the pair (L, L + 1).
+using WinLaunch = hipError_t (*)(const float*, int64_t, int, int, int, int, int, int, int,
+                                 int64_t, int64_t, double*, int32_t*, hipStream_t);
+template <int G, int... Ls>
+constexpr std::array<WinLaunch, sizeof...(Ls)> win_table(std::integer_sequence<int, Ls...>) {
+  return {&launch_win1<Ls + 1, G>...};
+}
+constexpr auto kWin1 = win_table<1>(std::make_integer_sequence<int, TRAKNN_MAX_L>{});
+constexpr auto kWin2 = win_table<2>(std::make_integer_sequence<int, TRAKNN_MAX_L - 1>{});
+
 size_t window1_lds_bytes(int L, int G, int k, int W) {
   return (size_t)G * W1_ROWS * sizeof(unsigned long long) +
          (size_t)W * (W1_VALS_BYTES(W1_ROWS + L - 1 + W1_GROUP) + (size_t)G * W1_ROWS * k * 12);
@@ -522,61 +535,9 @@ hipError_t launch_window_band(const float* S, int64_t ldS, int64_t T, int L_min,
     const int64_t hi = t0 + nt < T - L + 1 ? t0 + nt : T - L + 1;
     if (hi > t0) {
       const int a = (int)s0, b = (int)s_end, lo = (int)t0, cap = (int)(t0 + nt);
-      hipError_t e;
-      if (G == 2) {
-        switch (L) {
-#define TRAKNN_WIN2_CASE(n)                                                                  \
-  case n:                                                                                    \
-    e = launch_win1<n, 2>(S, ldS, (int)T, a, b, lo, cap, k, splits, split_stride, nt, pd, pi, \
-                          s);                                                                \
-    break;
-          TRAKNN_WIN2_CASE(1)
-          TRAKNN_WIN2_CASE(2)
-          TRAKNN_WIN2_CASE(3)
-          TRAKNN_WIN2_CASE(4)
-          TRAKNN_WIN2_CASE(5)
-          TRAKNN_WIN2_CASE(6)
-          TRAKNN_WIN2_CASE(7)
-          TRAKNN_WIN2_CASE(8)
-          TRAKNN_WIN2_CASE(9)
-          TRAKNN_WIN2_CASE(10)
-          TRAKNN_WIN2_CASE(11)
-          TRAKNN_WIN2_CASE(12)
-          TRAKNN_WIN2_CASE(13)
-          TRAKNN_WIN2_CASE(14)
-          TRAKNN_WIN2_CASE(15)
-#undef TRAKNN_WIN2_CASE
-          default:
-            return hipErrorInvalidValue;
-        }
-      } else {
-        switch (L) {
-#define TRAKNN_WIN1_CASE(n)                                                                  \
-  case n:                                                                                    \
-    e = launch_win1<n, 1>(S, ldS, (int)T, a, b, lo, cap, k, splits, split_stride, nt, pd, pi, \
-                          s);                                                                \
-    break;
-          TRAKNN_WIN1_CASE(1)
-          TRAKNN_WIN1_CASE(2)
-          TRAKNN_WIN1_CASE(3)
-          TRAKNN_WIN1_CASE(4)
-          TRAKNN_WIN1_CASE(5)
-          TRAKNN_WIN1_CASE(6)
-          TRAKNN_WIN1_CASE(7)
-          TRAKNN_WIN1_CASE(8)
-          TRAKNN_WIN1_CASE(9)
-          TRAKNN_WIN1_CASE(10)
-          TRAKNN_WIN1_CASE(11)
-          TRAKNN_WIN1_CASE(12)
-          TRAKNN_WIN1_CASE(13)
-          TRAKNN_WIN1_CASE(14)
-          TRAKNN_WIN1_CASE(15)
-          TRAKNN_WIN1_CASE(16)
-#undef TRAKNN_WIN1_CASE
-          default:
-            return hipErrorInvalidValue;
-        }
-      }
+      if (L < 1 || L + G - 1 > TRAKNN_MAX_L) return hipErrorInvalidValue;
+      const WinLaunch f = G == 2 ? kWin2[L - 1] : kWin1[L - 1];
+      const hipError_t e = f(S, ldS, (int)T, a, b, lo, cap, k, splits, split_stride, nt, pd, pi, s);
       if (e != hipSuccess) return e;
     }
     L += G;
