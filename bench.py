@@ -71,6 +71,18 @@ def gram_flops(T: int, D: int, prec: str) -> float:
     return passes * 2.0 * D * T * (T + 1) / 2.0
 
 
+def band_tiles(T: int, L_min: int, L_max: int, rb: int) -> int:
+    """256 x 256 Gram tiles of all band passes: pass t0 contracts its
+    ceil(rows / 256) block-rows I against the block-columns J >= t0 // 256 + I
+    (the tiles that hold entries above the diagonal)."""
+    n, nb, tiles = T - L_min + 1, -(-T // 256), 0
+    for t0 in range(0, n, rb):
+        srows = min(min(rb, n - t0) + L_max - 1, T - t0)
+        nbi, nbc = -(-srows // 256), nb - t0 // 256
+        tiles += nbi * nbc - nbi * (nbi - 1) // 2
+    return tiles
+
+
 def window_bytes(T: int, L: int, rows: int = 8) -> dict:
     """Bytes of S the window/top-k stage must read: the algorithmic figure is
     the upper triangle once (4 T(T+1)/2 B); this design reads every row of S
@@ -325,13 +337,8 @@ def main():
             f"{args.warmup} warmup + {args.compare_steps} steps")
         r = time_path(tk, torch, X, w, "bf16x3", args.compare_steps, args.warmup,
                       row_batch=args.band_rows)
-        # MFMA work of the band passes: every pass contracts ceil(rows / 256)
-        # block-rows of 256 fields against all T columns
-        rb, tiles = args.band_rows, 0
-        for t0 in range(0, n, rb):
-            srows = min(min(rb, n - t0) + w.L - 1, w.T - t0)
-            tiles += -(-srows // 256)
-        flops = 3 * 2.0 * w.D * (tiles * 256) * w.T
+        rb = args.band_rows
+        flops = 3 * 2.0 * w.D * 256 * 256 * band_tiles(w.T, w.L, w.L, rb)
         band = {"row_batch": rb, "ms_per_step": r["ms_per_step"],
                 "pairs_per_s": pairs / (r["ms_per_step"] * 1e-3),
                 "passes_ms": r["stage_ms"]["gram"],

@@ -93,17 +93,22 @@ extern "C" {
  *               (about 4 T^2 bytes) and only its upper-triangular tiles are
  *               contracted. > 0, a multiple of 8: band mode (row-batched
  *               streaming, for T whose matrix does not fit; the paper names
- *               out-of-core computation as future work, Sec. 7): each pass
- *               computes the rows t0 .. t0 + row_batch + L_max - 2 of the
- *               matrix against all T columns and emits the lists of
- *               trajectories t0 .. t0 + row_batch - 1, so the workspace holds
- *               (row_batch + L_max - 1) rows of it. A band cannot reuse the
- *               mirrored half, so the Gram work is about twice that of the
- *               whole-matrix mode, plus the part of each pass's last 256-row
- *               block-row beyond its rows (none when row_batch + L_max - 1 is a
- *               multiple of 256). Results agree with the whole-matrix mode
- *               within the precision's rounding (different summation order of
- *               the mirrored entries). */
+ *               out-of-core computation as future work, Sec. 7). Pass p owns
+ *               the trajectories t0 .. t0 + row_batch - 1 and computes the
+ *               rows t0 .. t0 + row_batch + L_max - 2 of the matrix against
+ *               the columns from t0 on, only the 256 x 256 tiles holding
+ *               entries above the diagonal, stored as rows and transposed.
+ *               Its rows' later candidates come from the rows, and every
+ *               later row's candidates among its trajectories from the
+ *               transposed copy (the matrix is symmetric); both are merged
+ *               into running lists, final for its rows when it ends. So the
+ *               Gram work is that of the whole-matrix mode plus about one
+ *               diagonal tile per 256-row block-row of each pass, and the
+ *               workspace holds (row_batch + L_max - 1) rows of the matrix
+ *               plus T rows of row_batch + L_max - 1 entries. Results agree
+ *               with the whole-matrix mode within the precision's rounding
+ *               (the band's tiles are aligned to its first row, not to
+ *               multiples of 256). */
 typedef struct {
   int64_t T;
   int64_t D;
@@ -139,7 +144,7 @@ int traknn_plan_destroy(traknn_plan_t plan);
 
 /* Exact exclusion-zone kNN over trajectories (paper, Algorithm 1 stages 1-3:
  * Eq. 4 Gram distances for the upper-triangular tile pairs -- or, in band
- * mode, for each pass's rows against all columns -- Eq. 5 diagonal
+ * mode, for each pass's rows against the later columns -- Eq. 5 diagonal
  * recurrence, k smallest with |t - j| > e).
  *   X         [in]  T x D fields, FP32, row-major with row stride ldx floats;
  *                   16-byte aligned, ldx >= D, ldx % 4 == 0.

@@ -23,10 +23,22 @@ constexpr size_t MAX_WIN_LDS = 64 * 1024;
 #define TRAKNN_WIN_TARGET_UNITS 12288
 #endif
 constexpr int64_t WIN_TARGET_UNITS = TRAKNN_WIN_TARGET_UNITS;
-constexpr int MAX_SPLITS = 16;
+// The same for the window launches of band mode, whose rows are shorter.
+#ifndef TRAKNN_BAND_WIN_TARGET_UNITS
+#define TRAKNN_BAND_WIN_TARGET_UNITS TRAKNN_WIN_TARGET_UNITS
+#endif
+constexpr int64_t BAND_WIN_TARGET_UNITS = TRAKNN_BAND_WIN_TARGET_UNITS;
+constexpr int MAX_SPLITS = MERGE_MAX_SPLITS;
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+// Row stride of a distance buffer, floats: whole 256-byte segments, an odd
+// number of them, so that rows a power of two apart do not all start in the
+// same HBM channel.
+int64_t matrix_stride(int64_t cols) {
+  const int64_t ld = round_up(cols, 64);
+  return (ld / 64) % 2 ? ld : ld + 64;
+}
 
 bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
@@ -34,29 +46,39 @@ int fail_hip(hipError_t e) { return e == hipSuccess ? TRAKNN_OK : TRAKNN_ERR_HIP
 
 // Column splits of the window stage: one workgroup of W waves per block of
 // WINDOW1_ROWS rows (the waves split the block's diagonals and share a per-row
-// bound), with W as large as the LDS budget and the target parallelism allow.
-// A multi-length request runs the same kernel once per length; L_max sizes
-// the LDS and the rows of the shortest length (of one pass in band mode) size
-// the grid.
-bool plan_window(traknn_plan_s* p) {
+// bound), with W as large as the LDS budget and the target parallelism allow,
+// for a launch of `rows` rows (of the shortest length) over `cands` candidate
+// columns. A multi-length request runs the same kernel once per length (or
+// pair of lengths); L_max sizes the LDS.
+int window_splits(const traknn_plan_s* p, int64_t rows, int64_t cands, int64_t target) {
   const int k = p->cfg.k;
   const int L = p->cfg.L_max;
-  const int64_t rows = p->rb ? (p->rb < p->np0 ? p->rb : p->np0) : p->np0;
   const int64_t nrb = (rows + WINDOW1_ROWS - 1) / WINDOW1_ROWS;
-  const int64_t nchunks = (p->np0 + WINDOW1_ROWS - 1 + 63) / 64;
+  const int64_t nchunks = (cands + WINDOW1_ROWS - 1 + 63) / 64;
   // a sweep's passes hold up to WINDOW_LENGTHS_PER_PASS lengths' lists
   const int G = p->NL > 1 ? WINDOW_LENGTHS_PER_PASS : 1;
   const size_t base = window1_lds_bytes(L, G, k, 0);
   const size_t per_wave = window1_lds_bytes(L, G, k, 1) - base;
-  if (base + per_wave > MAX_WIN_LDS) return false;
-  int64_t W = (WIN_TARGET_UNITS + nrb - 1) / nrb;
+  if (base + per_wave > MAX_WIN_LDS) return 0;
+  int64_t W = (target + nrb - 1) / nrb;
   const int64_t wmax = (int64_t)((MAX_WIN_LDS - base) / per_wave);
   if (W > wmax) W = wmax;
   if (W > MAX_SPLITS) W = MAX_SPLITS;
   if (W > nchunks) W = nchunks;
   if (W < 1) W = 1;
-  p->win_splits = (int)W;
-  return true;
+  return (int)W;
+}
+
+// Whole matrix: one launch of all rows over all columns. Band mode: per pass,
+// a row window of up to rb rows over the columns from the pass's first row on,
+// and a column window of the rows from the pass's first on over the pass's
+// (up to) rb trajectories.
+bool plan_window(traknn_plan_s* p) {
+  const int64_t rows = p->rb && p->rb < p->np0 ? p->rb : p->np0;
+  const int64_t target = p->rb ? BAND_WIN_TARGET_UNITS : WIN_TARGET_UNITS;
+  p->win_splits = window_splits(p, rows, p->np0, target);
+  p->col_splits = p->rb ? window_splits(p, p->np0, rows, target) : 0;
+  return p->win_splits > 0 && (!p->rb || p->col_splits > 0);
 }
 
 void plan_layout(traknn_plan_s* p) {
@@ -73,10 +95,17 @@ void plan_layout(traknn_plan_s* p) {
   L.ncs = take((size_t)norm_chunks(p->Dpad) * p->Tpad * sizeof(float));
   L.xc = take((size_t)p->Tpad * p->Dpad * elem_bytes(prec));
   L.S = take((size_t)(p->rb ? p->band_rows : p->T) * p->ldS * sizeof(float));
-  const int64_t prows = p->rb && p->rb < p->np0 ? p->rb : p->np0;  // rows of one pass
+  // band mode: the transposed band, one row per field
+  L.ST = take(p->rb ? (size_t)p->T * p->ldST * sizeof(float) : 0);
+  // partial lists: of the whole-matrix launch or a pass's row window (rb rows);
+  // band mode adds those of its first column window (every row)
+  const int64_t prows = p->rb && p->rb < p->np0 ? p->rb : p->np0;
   const size_t nparts = (size_t)p->win_splits * p->NL * prows * p->cfg.k;
   L.part_d = take(nparts * sizeof(double));
   L.part_i = take(nparts * sizeof(int32_t));
+  const size_t ncol = p->rb ? (size_t)p->col_splits * p->NL * p->np0 * p->cfg.k : 0;
+  L.cpart_d = take(ncol * sizeof(double));
+  L.cpart_i = take(ncol * sizeof(int32_t));
   const size_t np = (size_t)(p->T - p->cfg.L_min + 1);
   L.bw_cnt = take(np * sizeof(int32_t));
   L.bw_ptr = take((np + 1) * sizeof(int32_t));
@@ -161,12 +190,13 @@ int traknn_plan(const traknn_config* cfg, traknn_plan_t* out,
   p->rb = c.row_batch;
   // a band's last block-row may reach one tile past the last field
   p->Tpad = round_up(c.T, GRAM_TILE) + (p->rb ? GRAM_TILE : 0);
-  p->ldS = round_up(c.T, 64);
+  p->ldS = matrix_stride(c.T);
   p->np0 = c.T - c.L_min + 1;
   p->NL = c.L_max - c.L_min + 1;
   p->nb = (int)((c.T + GRAM_TILE - 1) / GRAM_TILE);
   p->ntiles = (int64_t)p->nb * (p->nb + 1) / 2;
   p->band_rows = p->rb + c.L_max - 1 < c.T ? p->rb + c.L_max - 1 : c.T;
+  p->ldST = p->rb ? matrix_stride(p->band_rows) : 0;
   p->tchunks = colstat_chunks(c.T);
   if (!plan_window(p)) {
     delete p;
@@ -248,25 +278,53 @@ int traknn_knn(traknn_plan_t plan, const float* X, int64_t ldx, void* workspace,
     return rc;
   if ((rc = record(plan, 2, s))) return rc;
   if (plan->rb) {
-    // band mode (row-batched streaming): per pass, the rows of S that the
-    // pass's trajectories reach, then their windows and lists
-    for (int64_t t0 = 0; t0 < plan->np0; t0 += plan->rb) {
-      const int64_t nt = plan->rb < plan->np0 - t0 ? plan->rb : plan->np0 - t0;
-      const int64_t srows = nt + c.L_max - 1 < plan->T - t0 ? nt + c.L_max - 1 : plan->T - t0;
+    // Band mode (row-batched streaming). Pass p owns the trajectories t0 ..
+    // t1 - 1; its band is the rows of S they reach, against the columns from
+    // t0 on (rounded down to a block-column), stored as rows and transposed.
+    // Only entries above the diagonal are computed and read:
+    // - Row window: the pass's rows over the later candidates (t0 .. n' - 1,
+    //   j > i), read from the band.
+    // - Column window: the rows t0 .. n' - 1 over the pass's earlier
+    //   candidates (t0 .. t1 - 1, j < i), read from the transposed band (S is
+    //   symmetric).
+    // One merge folds both into the rows' running lists; after pass p the rows
+    // t0 .. t1 - 1 are final. So every ordered pair of trajectories is a candidate
+    // exactly once, and the passes together contract about half the matrix.
+    float* ST = at<float>(workspace, L.ST);
+    double* cpart_d = at<double>(workspace, L.cpart_d);
+    int32_t* cpart_i = at<int32_t>(workspace, L.cpart_i);
+    const int64_t T = plan->T, np0 = plan->np0;
+    for (int64_t t0 = 0; t0 < np0; t0 += plan->rb) {
+      const int64_t nt = plan->rb < np0 - t0 ? plan->rb : np0 - t0;
+      const int64_t t1 = t0 + nt;
+      const int64_t srows = nt + c.L_max - 1 < T - t0 ? nt + c.L_max - 1 : T - t0;
       const int nbi = (int)((srows + GRAM_TILE - 1) / GRAM_TILE);
-      if ((rc = fail_hip(launch_gram_band(xc, ncs, plan->T, plan->Tpad, plan->Dpad, plan->nb,
-                                          (int64_t)nbi * plan->nb, c.precision, t0, nbi,
-                                          srows, S, plan->ldS, s))))
+      const int J0 = (int)(t0 / GRAM_TILE);
+      const int64_t c0 = (int64_t)J0 * GRAM_TILE;
+      const int64_t nbc = plan->nb - J0;  // block-columns from J0 on
+      const int64_t ntiles = nbi * nbc - (int64_t)nbi * (nbi - 1) / 2;
+      if ((rc = fail_hip(launch_gram_band(xc, ncs, T, plan->Tpad, plan->Dpad, plan->nb, ntiles,
+                                          c.precision, t0, nbi, srows, J0, S, plan->ldS, ST,
+                                          plan->ldST, s))))
         return rc;
-      if ((rc = fail_hip(launch_window_band(S, plan->ldS, plan->T, c.L_min, c.L_max, c.k,
-                                            plan->win_splits, t0, t0 + srows, t0, nt,
-                                            part_d, part_i, s))))
+      const WindowRange rows{t0, t0 + srows, c0, t0, T, T, 1, T};
+      if ((rc = fail_hip(launch_window_band(S, plan->ldS, T, c.L_min, c.L_max, c.k,
+                                            plan->win_splits, rows, t0, nt, part_d, part_i,
+                                            s))))
         return rc;
-      if ((rc = fail_hip(launch_merge_band(part_d, part_i, plan->T, c.L_min, c.L_max, c.k,
-                                           plan->win_splits, t0, nt, nbr_idx, nbr_dist, s))))
+      const WindowRange cols{c0, T, t0, t0, t1, t0 + srows, -T, -1};
+      if ((rc = fail_hip(launch_window_band(ST, plan->ldST, T, c.L_min, c.L_max, c.k,
+                                            plan->col_splits, cols, t0, np0 - t0, cpart_d,
+                                            cpart_i, s))))
+        return rc;
+      // every row from t0 on holds the earlier passes' lists (none in pass 0)
+      const MergeSet mr{part_d, part_i, plan->win_splits, (int)nt};
+      const MergeSet mc{cpart_d, cpart_i, plan->col_splits, (int)(np0 - t0)};
+      if ((rc = fail_hip(launch_merge_band(mr, mc, T, c.L_min, c.L_max, c.k, t0, np0 - t0,
+                                           t0 > 0 ? np0 : 0, nbr_idx, nbr_dist, s))))
         return rc;
     }
-    // the passes interleave the three stages: the Gram slot times them all
+    // the passes interleave the stages: the Gram slot times them all
     if ((rc = record(plan, 3, s))) return rc;
     if ((rc = record(plan, 4, s))) return rc;
     if ((rc = record(plan, 5, s))) return rc;

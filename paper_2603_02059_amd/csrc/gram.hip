@@ -27,10 +27,12 @@
 // an XCD runs at once then share 4 A panels and ~8 B panels in its L2.
 //
 // Band mode (row-batched streaming, for T whose T x T matrix does not fit):
-// the kernel fills a band of rows a_row0 .. a_row0 + rows_out - 1 against all
-// T columns, every tile (I, J) of the rectangle computed directly and stored
-// once, into a buffer whose row 0 is field a_row0. Symmetry cannot be used
-// there, since the mirrored rows belong to other bands.
+// the kernel fills a band of rows a_row0 .. a_row0 + rows_out - 1 against the
+// columns from block-column J0 on (the columns before it belong to earlier
+// bands), every tile (I, J) of the rectangle that holds an entry above the
+// diagonal computed directly. It is stored twice: as rows, into a buffer
+// whose row 0 is field a_row0 and column 0 field 256 J0, and transposed, so
+// that the later fields' rows of the band's columns are contiguous too.
 #include <type_traits>
 
 #include "internal.h"
@@ -74,15 +76,16 @@ __device__ __forceinline__ int swz(int row, int chunk) {
   return ((chunk ^ swz_key(row)) << 4);
 }
 
-// Tile id -> (I, J), I <= J, in the XCD-aware grouped order described above.
-__device__ __forceinline__ bool decode_tile(int64_t wg, int nb, int64_t ntiles,
+// Tile id -> (I, J), I <= J < nb, I < nrows (<= nb), in the XCD-aware
+// grouped order described above; ntiles = nrows nb - nrows (nrows - 1) / 2.
+__device__ __forceinline__ bool decode_tile(int64_t wg, int nb, int nrows, int64_t ntiles,
                                             int& I, int& J) {
   const int64_t per = (ntiles + NUM_XCD - 1) / NUM_XCD;
   const int64_t lin = (wg % NUM_XCD) * per + wg / NUM_XCD;
   if (lin >= ntiles) return false;
   int64_t u = lin;
-  for (int I0 = 0; I0 < nb; I0 += GRAM_GROUP_ROWS) {
-    const int gm = nb - I0 < GRAM_GROUP_ROWS ? nb - I0 : GRAM_GROUP_ROWS;
+  for (int I0 = 0; I0 < nrows; I0 += GRAM_GROUP_ROWS) {
+    const int gm = nrows - I0 < GRAM_GROUP_ROWS ? nrows - I0 : GRAM_GROUP_ROWS;
     const int64_t cnt = (int64_t)gm * nb - ((int64_t)gm * I0 + (int64_t)gm * (gm - 1) / 2);
     if (u < cnt) {
       const int64_t head = (int64_t)gm * (gm - 1) / 2;
@@ -102,22 +105,6 @@ __device__ __forceinline__ bool decode_tile(int64_t wg, int nb, int64_t ntiles,
     u -= cnt;
   }
   return false;
-}
-
-// Band mode: tile id -> (I, J) over nbi band block-rows x nb block-columns,
-// in the same grouped, XCD-aware order.
-__device__ __forceinline__ bool decode_rect(int64_t wg, int nbi, int nb, int64_t ntiles,
-                                            int& I, int& J) {
-  const int64_t per = (ntiles + NUM_XCD - 1) / NUM_XCD;
-  const int64_t lin = (wg % NUM_XCD) * per + wg / NUM_XCD;
-  if (lin >= ntiles) return false;
-  const int64_t grp = (int64_t)GRAM_GROUP_ROWS * nb;  // tiles of a full group
-  const int I0 = (int)(lin / grp) * GRAM_GROUP_ROWS;
-  const int64_t u = lin % grp;
-  const int gm = nbi - I0 < GRAM_GROUP_ROWS ? nbi - I0 : GRAM_GROUP_ROWS;
-  J = (int)(u / gm);
-  I = I0 + (int)(u % gm);
-  return true;
 }
 
 // Scheduling-group masks for __builtin_amdgcn_sched_group_barrier.
@@ -239,14 +226,18 @@ template <int PREC, bool BAND>
 __global__ __launch_bounds__(GRAM_THREADS, 1) void gram_kernel(
     const char* __restrict__ xc, int64_t pitch, int nstages,
     const float* __restrict__ ncs, int64_t T, int64_t Tpad, int nb, int64_t ntiles,
-    int64_t a_row0, int nbi, int64_t rows_out, float* __restrict__ S, int64_t ldS) {
+    int64_t a_row0, int nbi, int64_t rows_out, int J0, float* __restrict__ S, int64_t ldS,
+    float* __restrict__ ST, int64_t ldST) {
   __shared__ __attribute__((aligned(16))) char lds[GRAM_STAGES * 2 * OPER_BYTES + NORM_LDS];
   float* const nrm = (float*)(lds + GRAM_STAGES * 2 * OPER_BYTES);  // [2][I 256 | J 256]
   int I, J;
   if constexpr (BAND) {
-    if (!decode_rect(blockIdx.x, nbi, nb, ntiles, I, J)) return;
+    // the band's tiles that hold entries above the diagonal: J >= J0 + I,
+    // the upper triangle of the columns from J0 on, cut to the band's rows
+    if (!decode_tile(blockIdx.x, nb - J0, nbi, ntiles, I, J)) return;
+    J += J0;
   } else {
-    if (!decode_tile(blockIdx.x, nb, ntiles, I, J)) return;
+    if (!decode_tile(blockIdx.x, nb, nb, ntiles, I, J)) return;
   }
   // first fields of the tile's A and B panels
   const int64_t arow = (BAND ? a_row0 : 0) + (int64_t)I * TILE;
@@ -396,6 +387,7 @@ __global__ __launch_bounds__(GRAM_THREADS, 1) void gram_kernel(
   float* stg = (float*)lds;  // [NWAVES][WT_N][EPI_PITCH]
   const bool diag = !BAND && I == J;
   const int64_t i_base = (int64_t)I * TILE, j_base = (int64_t)J * TILE;
+  const int64_t c0 = BAND ? (int64_t)J0 * TILE : 0;  // first column held in band mode
 #pragma unroll
   for (int bm = 0; bm < BM; ++bm) {
     float* mine = stg + w * WT_N * EPI_PITCH;
@@ -427,13 +419,14 @@ __global__ __launch_bounds__(GRAM_THREADS, 1) void gram_kernel(
             const float v = -2.f * src[r];
             // band mode: a field's distance to itself is stored as 0, as the
             // mirrored pass stores it in the symmetric mode
-            S[i * ldS + j] = (BAND && a_row0 + i == j) ? 0.f : (v > 0.f ? v : 0.f);
+            S[i * ldS + (j - c0)] = (BAND && a_row0 + i == j) ? 0.f : (v > 0.f ? v : 0.f);
           }
         }
       }
     }
-    // (j, i): 8 threads per (column, row half) write 32 consecutive i (symmetric mode only)
-    if constexpr (!BAND) {
+    // (j, i): 8 threads per (column, row half) write 32 consecutive i, into S
+    // itself or, in band mode, into the transposed band
+    {
       for (int run = tid >> 3; run < WAVES_M * TILE; run += GRAM_THREADS / 8) {
         const int jl = run / WAVES_M, wm_ = run % WAVES_M;
         const int wn_ = jl / WT_N, c = jl % WT_N;
@@ -450,16 +443,29 @@ __global__ __launch_bounds__(GRAM_THREADS, 1) void gram_kernel(
           const float v = -2.f * g[e];
           f[e] = v > 0.f ? v : 0.f;
         }
-        float* dst = S + j * ldS + i0;
-        if (!diag && i0 + 3 < T) {
-          *(f32x4*)dst = f32x4{f[0], f[1], f[2], f[3]};
-        } else {
+        if constexpr (BAND) {
+          // i0 is a band row: field a_row0 + i0
+          float* dst = ST + (j - c0) * ldST + i0;
+          const int64_t dj = j - (a_row0 + i0);  // field j's position in the run, if any
+          if (i0 + 3 < rows_out && (dj < 0 || dj > 3)) {
+            *(f32x4*)dst = f32x4{f[0], f[1], f[2], f[3]};
+          } else {
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const int il = il0 + e;
-            if (i0 + e >= T) continue;
-            if (!diag || il < jl) dst[e] = f[e];
-            else if (il == jl) dst[e] = 0.f;
+            for (int e = 0; e < 4; ++e)
+              if (i0 + e < rows_out) dst[e] = dj == e ? 0.f : f[e];
+          }
+        } else {
+          float* dst = S + j * ldS + i0;
+          if (!diag && i0 + 3 < T) {
+            *(f32x4*)dst = f32x4{f[0], f[1], f[2], f[3]};
+          } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              const int il = il0 + e;
+              if (i0 + e >= T) continue;
+              if (!diag || il < jl) dst[e] = f[e];
+              else if (il == jl) dst[e] = 0.f;
+            }
           }
         }
       }
@@ -473,13 +479,14 @@ __global__ __launch_bounds__(GRAM_THREADS, 1) void gram_kernel(
 hipError_t launch_gram(const void* xc, const float* ncs, int64_t T, int64_t Tpad,
                        int64_t Dpad, int nb, int64_t ntiles, int precision,
                        float* S, int64_t ldS, hipStream_t s) {
-  return launch_gram_band(xc, ncs, T, Tpad, Dpad, nb, ntiles, precision, -1, 0, 0, S, ldS, s);
+  return launch_gram_band(xc, ncs, T, Tpad, Dpad, nb, ntiles, precision, -1, 0, 0, 0, S, ldS,
+                          nullptr, 0, s);
 }
 
 hipError_t launch_gram_band(const void* xc, const float* ncs, int64_t T, int64_t Tpad,
                             int64_t Dpad, int nb, int64_t ntiles, int precision,
-                            int64_t a_row0, int nbi, int64_t rows_out, float* S,
-                            int64_t ldS, hipStream_t s) {
+                            int64_t a_row0, int nbi, int64_t rows_out, int J0, float* S,
+                            int64_t ldS, float* ST, int64_t ldST, hipStream_t s) {
   const int64_t pitch = Dpad * elem_bytes(precision);
   const int nstages = (int)(Dpad / stage_k(precision));
   const int64_t per = (ntiles + NUM_XCD - 1) / NUM_XCD;
@@ -489,7 +496,7 @@ hipError_t launch_gram_band(const void* xc, const float* ncs, int64_t T, int64_t
   if (!band) rows_out = T;
 #define TRAKNN_GRAM_LAUNCH(P, B)                                                          \
   hipLaunchKernelGGL((gram_kernel<P, B>), grid, dim3(GRAM_THREADS), 0, s, x, pitch, nstages, \
-                     ncs, T, Tpad, nb, ntiles, a_row0, nbi, rows_out, S, ldS)
+                     ncs, T, Tpad, nb, ntiles, a_row0, nbi, rows_out, J0, S, ldS, ST, ldST)
   switch (precision) {
     case TRAKNN_FP32:
       if (band) TRAKNN_GRAM_LAUNCH(TRAKNN_FP32, true);

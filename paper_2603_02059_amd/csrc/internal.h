@@ -48,7 +48,8 @@ inline int colstat_chunks(int64_t T) {
 }
 
 struct Layout {
-  size_t mu_part, mu, ncs, xc, S, part_d, part_i;  // forward
+  size_t mu_part, mu, ncs, xc, S, ST, part_d, part_i;  // forward
+  size_t cpart_d, cpart_i;                             // band mode: column windows
   size_t bw_cnt, bw_ptr, bw_fill, bw_rev;            // backward
   size_t total;
 };
@@ -67,8 +68,10 @@ struct traknn_plan_s {
   int64_t ntiles;    // nb (nb + 1) / 2 upper-triangular tile pairs
   int64_t rb;        // band mode: trajectory rows per pass (0: whole matrix)
   int64_t band_rows; // band mode: rows of S held, rb + L_max - 1 (at most T)
+  int64_t ldST;      // band mode: row stride of the transposed band, floats
   int tchunks;       // partial column-sum blocks of the sampled rows
   int win_splits;    // column splits (waves) per window row block (W)
+  int col_splits;    // band mode: the same for the column windows
   traknn::Layout lay;
   // timing
   int timing;
@@ -92,12 +95,17 @@ hipError_t launch_gram(const void* xc, const float* ncs, int64_t T, int64_t Tpad
                        int64_t Dpad, int nb, int64_t ntiles, int precision,
                        float* S, int64_t ldS, hipStream_t s);
 // Band mode: rows a_row0 .. a_row0 + rows_out - 1 (nbi = ceil(rows_out / 256)
-// block-rows, ntiles = nbi * nb) against every column, into S whose row 0 is
-// field a_row0. a_row0 must be a multiple of 4 and a_row0 + nbi * 256 <= Tpad.
+// block-rows) against the columns of block-columns J0 = a_row0 / 256 .. nb -
+// 1. Only the tiles J >= J0 + I, those that hold entries above the diagonal,
+// are computed (ntiles = nbi nb' - nbi (nbi - 1) / 2 with nb' = nb - J0); the
+// rest of both buffers is left unwritten. Field j of row a_row0 + i goes to
+// S[i * ldS + j - 256 J0] and, transposed, to ST[(j - 256 J0) * ldST + i].
+// a_row0 must be a multiple of 8, nbi <= nb', a_row0 + nbi * 256 <= Tpad and
+// ldST >= rows_out, a multiple of 4.
 hipError_t launch_gram_band(const void* xc, const float* ncs, int64_t T, int64_t Tpad,
                             int64_t Dpad, int nb, int64_t ntiles, int precision,
-                            int64_t a_row0, int nbi, int64_t rows_out, float* S,
-                            int64_t ldS, hipStream_t s);
+                            int64_t a_row0, int nbi, int64_t rows_out, int J0, float* S,
+                            int64_t ldS, float* ST, int64_t ldST, hipStream_t s);
 // window_topk.hip
 hipError_t launch_window_topk(const float* S, int64_t ldS, int64_t T, int L_min,
                               int L_max, int k, int splits, double* part_d,
@@ -105,16 +113,34 @@ hipError_t launch_window_topk(const float* S, int64_t ldS, int64_t T, int L_min,
 hipError_t launch_merge(const double* part_d, const int32_t* part_i, int64_t T,
                         int L_min, int L_max, int k, int splits, int32_t* idx,
                         double* dist, hipStream_t s);
-// Band mode: S holds rows s0 .. s_end - 1 (its row 0 is row s0); the lists of
-// trajectory rows t0 .. t0 + nt - 1 (counted for L_min; fewer for longer L)
-// go to partial lists indexed from t0, which launch_merge_band combines into
-// rows t0 .. of idx and dist.
+// The part of the matrix a window launch sees: S holds rows s0 .. s_end - 1
+// (its row 0 is row s0) and column c at column c - col0; candidates are the
+// columns c_lo .. c_hi - 1 at diagonal offsets j - i in dmin .. dmax, values
+// are read in the columns c_lo .. v_end - 1 and relied on only on the
+// diagonals of that offset range. The whole matrix is {0, T, 0, 0, T, T, -T, T}.
+struct WindowRange {
+  int64_t s0, s_end, col0, c_lo, c_hi, v_end, dmin, dmax;
+};
+// The lists of trajectory rows t0 .. t0 + nt - 1 (counted for L_min; fewer for
+// longer L) over the candidates of r go to partial lists indexed from t0:
+// [split][length][row - t0][k].
 hipError_t launch_window_band(const float* S, int64_t ldS, int64_t T, int L_min,
-                              int L_max, int k, int splits, int64_t s0, int64_t s_end,
+                              int L_max, int k, int splits, const WindowRange& r,
                               int64_t t0, int64_t nt, double* part_d, int32_t* part_i,
                               hipStream_t s);
-hipError_t launch_merge_band(const double* part_d, const int32_t* part_i, int64_t T,
-                             int L_min, int L_max, int k, int splits, int64_t t0, int64_t nt,
+// One window launch's partial lists, as the merge reads them: W splits of the
+// rows t0 .. t0 + nt - 1.
+constexpr int MERGE_MAX_SPLITS = 16;
+struct MergeSet {
+  const double* d;
+  const int32_t* i;
+  int W, nt;
+};
+// Rows t0 .. t0 + nt - 1 of idx and dist become the k smallest of the lists
+// of sets a and b (both indexed from t0, each covering its first nt rows) and,
+// for the rows below acc_end, of the lists already there.
+hipError_t launch_merge_band(const MergeSet& a, const MergeSet& b, int64_t T, int L_min,
+                             int L_max, int k, int64_t t0, int64_t nt, int64_t acc_end,
                              int32_t* idx, double* dist, hipStream_t s);
 hipError_t launch_score(const double* dist, int64_t T, int L_min, int L_max,
                         int k, double* scores, hipStream_t s);

@@ -16,9 +16,14 @@
 // is one compare per lane against that row's bound and one ballot; the rare
 // insertions shift a sorted list held one entry per lane.
 //
-// In band mode (row-batched streaming) S holds only rows s0 .. s_end - 1 of the
-// matrix, and a launch covers the trajectory rows row_lo .. row_cap - 1 whose
-// windows lie inside them; its partial lists are indexed from row_lo.
+// A launch may cover part of the matrix (band mode, row-batched streaming):
+// S then holds rows s0 .. s_end - 1, and column c of the matrix at column
+// c - col0 of the buffer; the launch covers the trajectory rows row_lo ..
+// row_cap - 1 against the candidate columns c_lo .. c_hi - 1 whose diagonal
+// offset j - i lies in dmin .. dmax, reads values only in columns c_lo ..
+// v_end - 1 (zero elsewhere, which leaves the windows of valid candidates
+// exact), and indexes its partial lists from row_lo. Only the diagonals of
+// the offset range are visited, and only their values are relied on.
 //
 // A multi-length request (L = L_min .. L_max) runs the kernel once per pair of
 // lengths on the same distance matrix, each length with its own running sums,
@@ -169,9 +174,10 @@ __device__ __forceinline__ void seed_row(double d, int c, bool valid, int k, dou
 // as in a pass of its own, so the results do not depend on G.
 template <int L, int G>
 __global__ __launch_bounds__(1024) void window1_kernel(
-    const float* __restrict__ S, int64_t ldS, int T, int s0, int s_end, int row_lo,
-    int row_cap, int k, int W, int64_t split_stride, int64_t len_rows,
-    double* __restrict__ part_d, int32_t* __restrict__ part_i) {
+    const float* __restrict__ S, int64_t ldS, int T, int s0, int s_end, int col0, int c_lo,
+    int c_hi, int v_end, int dmin, int dmax, int row_lo, int row_cap, int k, int W,
+    int64_t split_stride, int64_t len_rows, double* __restrict__ part_d,
+    int32_t* __restrict__ part_i) {
   constexpr int R = W1_ROWS;
   constexpr int U = W1_GROUP;
   constexpr int LG = L + G - 1;  // longest length of the pass
@@ -190,16 +196,24 @@ __global__ __launch_bounds__(1024) void window1_kernel(
   __syncthreads();  // the only workgroup barrier: the waves' trip counts differ
 
   const int r0 = row_lo + (int)blockIdx.x * R;
-  int npl[G];    // candidate trajectories (columns) of each length
+  int chi[G];    // candidate columns of each length: c_lo .. chi - 1
+  int ncand[G];  // chi - c_lo, at least 0
   int nrows[G];  // rows of this block that exist for each length
 #pragma unroll
   for (int g = 0; g < G; ++g) {
-    npl[g] = T - (L + g) + 1;
-    const int hi = row_cap < npl[g] ? row_cap : npl[g];
+    const int npl = T - (L + g) + 1;  // trajectories of length L + g
+    chi[g] = c_hi < npl ? c_hi : npl;
+    ncand[g] = chi[g] > c_lo ? chi[g] - c_lo : 0;
+    const int hi = row_cap < npl ? row_cap : npl;
     nrows[g] = hi - r0 < R ? (hi - r0 > 0 ? hi - r0 : 0) : R;
   }
-  const int64_t dlo = -(int64_t)(r0 + R - 1);
-  const int64_t NC = ((int64_t)npl[0] + R - 1 + 63) / 64;
+  // diagonals of the block: every candidate column of some row, within the
+  // offset range
+  int64_t dlo = (int64_t)c_lo - (r0 + R - 1);
+  if (dlo < dmin) dlo = dmin;
+  int64_t dhi = (int64_t)chi[0] - 1 - r0;
+  if (dhi > dmax) dhi = dmax;
+  const int64_t NC = ncand[0] > 0 && dhi >= dlo ? (dhi - dlo + 1 + 63) / 64 : 0;
   const int64_t cb = (int64_t)split * NC / W, ce = (int64_t)(split + 1) * NC / W;
 
   double thr_d[G];  // lane q: own k-th of row r0 + q, per length
@@ -211,7 +225,8 @@ __global__ __launch_bounds__(1024) void window1_kernel(
   }
 
   // Values of diagonal delta at rows r0 + m (one 256-byte segment per row
-  // for the wave), zero outside the matrix. The pointer walks down the rows
+  // for the wave), zero outside the held rows and the columns c_lo ..
+  // v_end - 1. The pointer walks down the rows
   // with a stride the compiler treats as opaque, so no per-row address is
   // precomputed and held across chunks; chunks wholly inside the matrix skip
   // the bounds tests, the others read a safe element and discard it.
@@ -220,8 +235,8 @@ __global__ __launch_bounds__(1024) void window1_kernel(
     const int64_t dc = dlo + 64 * c;
     int64_t stride = ldS + 1;
     asm volatile("" : "+s"(stride));
-    const float* p = S + ((int64_t)(r0 - s0) * ldS + r0 + dc + lane);
-    const bool inb = r0 + dc >= 0 && r0 + M - 1 < s_end && r0 + M - 1 + dc + 63 < T;
+    const float* p = S + ((int64_t)(r0 - s0) * ldS + (r0 + dc + lane - col0));
+    const bool inb = r0 + dc >= c_lo && r0 + M - 1 < s_end && r0 + M - 1 + dc + 63 < v_end;
     if (inb) {
 #pragma unroll
       for (int m = 0; m < M; ++m) {
@@ -230,12 +245,12 @@ __global__ __launch_bounds__(1024) void window1_kernel(
       }
     } else {
       int rows_in = s_end - r0;  // rows r0 + m with m < rows_in are held
-      int64_t Tl = T;
-      asm volatile("" : "+s"(rows_in), "+s"(Tl));
+      int64_t vlo = c_lo, vhi = v_end;
+      asm volatile("" : "+s"(rows_in), "+s"(vlo), "+s"(vhi));
       int64_t col = r0 + dc + lane;  // column of row r0 + m, stepped with m
 #pragma unroll
       for (int m = 0; m < M; ++m) {
-        const bool ok = (m < rows_in) & (col >= 0) & (col < Tl);
+        const bool ok = (m < rows_in) & (col >= vlo) & (col < vhi);
         const float x = *(ok ? p : S);
         nxt[m] = ok ? x : 0.f;
         p += stride;
@@ -256,14 +271,14 @@ __global__ __launch_bounds__(1024) void window1_kernel(
 #pragma unroll
     for (int g = 0; g < G; ++g) {
       const int Lg = L + g;
-      const bool okd = (delta >= Lg) | (delta <= -Lg);
+      const bool okd = ((delta >= Lg) | (delta <= -Lg)) & (delta >= dmin) & (delta <= dmax);
       double D = 0.0;
 #pragma unroll
       for (int l = 0; l < L + g; ++l) D += (double)vl[l * 64 + lane];
 #pragma unroll 1
       for (int s = 0; s < nrows[g]; ++s) {
         const int col = r0 + s + delta;
-        const bool valid = okd & ((unsigned)col < (unsigned)npl[g]);
+        const bool valid = okd & ((unsigned)(col - c_lo) < (unsigned)ncand[g]);
         seed_row(D, col, valid, k, ld + (g * R + s) * k, li + (g * R + s) * k, lane, s,
                  thr_d[g], thr_i[g]);
         publish(g, s);
@@ -281,7 +296,7 @@ __global__ __launch_bounds__(1024) void window1_kernel(
     double D[G];
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-      okd[g] = (delta >= L + g) | (delta <= -(L + g));
+      okd[g] = ((delta >= L + g) | (delta <= -(L + g))) & (delta >= dmin) & (delta <= dmax);
       D[g] = 0.0;
 #pragma unroll
       for (int l = 0; l < L + g; ++l) D[g] += (double)vl[l * 64 + lane];
@@ -312,7 +327,8 @@ __global__ __launch_bounds__(1024) void window1_kernel(
           bool pass = D[g] <= readlane_d(bound[g], s);
           if constexpr (EDGE) {
             const int col = r0 + s + delta;
-            pass = pass & okd[g] & ((unsigned)col < (unsigned)npl[g]) & (s < nrows[g]);
+            pass = pass & okd[g] & ((unsigned)(col - c_lo) < (unsigned)ncand[g]) &
+                   (s < nrows[g]);
           }
           m[g][j] = __ballot(pass);
           any |= m[g][j];
@@ -349,8 +365,9 @@ __global__ __launch_bounds__(1024) void window1_kernel(
     __builtin_amdgcn_wave_barrier();
     if (c + 1 < ce) load(c + 1);
     const int64_t dc = dlo + 64 * c;
-    const bool interior = full & ((dc >= LG) | (dc + 63 <= -LG)) & (r0 + dc >= 0) &
-                          (r0 + R - 1 + dc + 63 < npl[G - 1]);
+    const bool interior = full & ((dc >= LG) | (dc + 63 <= -LG)) & (r0 + dc >= c_lo) &
+                          (r0 + R - 1 + dc + 63 < chi[G - 1]) & (dc >= dmin) &
+                          (dc + 63 <= dmax);
     if (c == cb)
       seed_chunk(c);
     else if (interior)
@@ -376,22 +393,26 @@ __global__ __launch_bounds__(1024) void window1_kernel(
 // Row blocks of lengths L .. L + G - 1: ceil((rows of length L) / W1_ROWS)
 // workgroups of W waves.
 template <int L, int G>
-hipError_t launch_win1(const float* S, int64_t ldS, int T, int s0, int s_end, int row_lo,
+hipError_t launch_win1(const float* S, int64_t ldS, int T, int s0, int s_end, int col0,
+                       int c_lo, int c_hi, int v_end, int dmin, int dmax, int row_lo,
                        int row_cap, int k, int W, int64_t split_stride, int64_t len_rows,
                        double* pd, int32_t* pi, hipStream_t s) {
   const size_t lds = window1_lds_bytes(L + G - 1, G, k, W);
   const int hi = row_cap < T - L + 1 ? row_cap : T - L + 1;
   const unsigned blocks = (unsigned)((hi - row_lo + W1_ROWS - 1) / W1_ROWS);
   hipLaunchKernelGGL((window1_kernel<L, G>), dim3(blocks), dim3(64 * W), lds, s, S, ldS, T,
-                     s0, s_end, row_lo, row_cap, k, W, split_stride, len_rows, pd, pi);
+                     s0, s_end, col0, c_lo, c_hi, v_end, dmin, dmax, row_lo, row_cap, k, W,
+                     split_stride, len_rows, pd, pi);
   return hipGetLastError();
 }
 
 __global__ __launch_bounds__(256) void merge_kernel(
-    const double* __restrict__ part_d, const int32_t* __restrict__ part_i,
-    int T, int np0, int Lmin, int NL, int k, int W, int t0, int nt,
-    int32_t* __restrict__ idx, double* __restrict__ dist) {
-  // rows t0 .. t0 + nt - 1 of every length; partial lists indexed from t0
+    MergeSet a, MergeSet b, int T, int np0, int Lmin, int NL, int k, int t0, int nt,
+    int acc_end, int32_t* __restrict__ idx, double* __restrict__ dist) {
+  // rows t0 .. t0 + nt - 1 of every length. A set's partial lists are indexed
+  // from t0 and cover its first rows only; for the rows below acc_end the list
+  // already in the output (a running list of earlier launches, empty slots as
+  // index -1) is one more sorted source.
   const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (g >= (int64_t)NL * nt) return;
   const int li = (int)(g / nt);
@@ -407,25 +428,43 @@ __global__ __launch_bounds__(256) void merge_kernel(
     }
     return;
   }
-  constexpr int MAXW = 64;
-  int pos[MAXW];
-  for (int w = 0; w < W; ++w) pos[w] = 0;
+  double rd[TRAKNN_MAX_K];
+  int ri[TRAKNN_MAX_K];
+  const int nr = t < acc_end ? k : 0;
+  for (int q = 0; q < nr; ++q) {
+    rd[q] = od[q];
+    ri[q] = oi[q] < 0 ? INT_MAX : oi[q];
+  }
+  const int wa = tr < a.nt ? a.W : 0, wb = tr < b.nt ? b.W : 0;
+  const int ns = wa + wb;  // partial-list sources
+  int pos[2 * MERGE_MAX_SPLITS];
+  for (int w = 0; w < ns; ++w) pos[w] = 0;
+  int rpos = 0;
   for (int q = 0; q < k; ++q) {
-    int best = -1;
+    int best = -1;  // source: a partial list w, or ns for the running list
     double bd = 0.0;
     int bi = INT_MAX;
-    for (int w = 0; w < W; ++w) {
+    if (rpos < nr) {
+      best = ns;
+      bd = rd[rpos];
+      bi = ri[rpos];
+    }
+    for (int w = 0; w < ns; ++w) {
       if (pos[w] >= k) continue;
-      const int64_t o = (((int64_t)w * NL + li) * nt + tr) * k + pos[w];
-      const double d = part_d[o];
-      const int i = part_i[o];
+      const bool in_a = w < wa;
+      const MergeSet& m = in_a ? a : b;
+      const int ws = in_a ? w : w - wa;
+      const int64_t o = (((int64_t)ws * NL + li) * m.nt + tr) * k + pos[w];
+      const double d = m.d[o];
+      const int i = m.i[o];
       if (best < 0 || key_less(d, i, bd, bi)) {
         best = w;
         bd = d;
         bi = i;
       }
     }
-    pos[best]++;
+    if (best == ns) rpos++;
+    else pos[best]++;
     oi[q] = bi == INT_MAX ? -1 : bi;
     od[q] = bd;
   }
@@ -495,8 +534,9 @@ __global__ __launch_bounds__(256) void local_dim_kernel(
 
 // Launchers of every compiled (L, G): kWin1[L - 1] for L = 1..TRAKNN_MAX_L on
 // its own, kWin2[L - 1] for the pair (L, L + 1).
-using WinLaunch = hipError_t (*)(const float*, int64_t, int, int, int, int, int, int, int,
-                                 int64_t, int64_t, double*, int32_t*, hipStream_t);
+using WinLaunch = hipError_t (*)(const float*, int64_t, int, int, int, int, int, int, int, int,
+                                 int, int, int, int, int, int64_t, int64_t, double*, int32_t*,
+                                 hipStream_t);
 template <int G, int... Ls>
 constexpr std::array<WinLaunch, sizeof...(Ls)> win_table(std::integer_sequence<int, Ls...>) {
   return {&launch_win1<Ls + 1, G>...};
@@ -512,12 +552,13 @@ size_t window1_lds_bytes(int L, int G, int k, int W) {
 hipError_t launch_window_topk(const float* S, int64_t ldS, int64_t T, int L_min,
                               int L_max, int k, int splits, double* part_d,
                               int32_t* part_i, hipStream_t s) {
-  return launch_window_band(S, ldS, T, L_min, L_max, k, splits, 0, T, 0, T - L_min + 1,
-                            part_d, part_i, s);
+  const WindowRange all{0, T, 0, 0, T, T, -T, T};
+  return launch_window_band(S, ldS, T, L_min, L_max, k, splits, all, 0, T - L_min + 1, part_d,
+                            part_i, s);
 }
 
 hipError_t launch_window_band(const float* S, int64_t ldS, int64_t T, int L_min,
-                              int L_max, int k, int splits, int64_t s0, int64_t s_end,
+                              int L_max, int k, int splits, const WindowRange& r,
                               int64_t t0, int64_t nt, double* part_d, int32_t* part_i,
                               hipStream_t s) {
   const int NL = L_max - L_min + 1;
@@ -534,10 +575,12 @@ hipError_t launch_window_band(const float* S, int64_t ldS, int64_t T, int L_min,
     // of the pass have fewer; none at all means the merge marks them absent)
     const int64_t hi = t0 + nt < T - L + 1 ? t0 + nt : T - L + 1;
     if (hi > t0) {
-      const int a = (int)s0, b = (int)s_end, lo = (int)t0, cap = (int)(t0 + nt);
       if (L < 1 || L + G - 1 > TRAKNN_MAX_L) return hipErrorInvalidValue;
       const WinLaunch f = G == 2 ? kWin2[L - 1] : kWin1[L - 1];
-      const hipError_t e = f(S, ldS, (int)T, a, b, lo, cap, k, splits, split_stride, nt, pd, pi, s);
+      const hipError_t e =
+          f(S, ldS, (int)T, (int)r.s0, (int)r.s_end, (int)r.col0, (int)r.c_lo, (int)r.c_hi,
+            (int)r.v_end, (int)r.dmin, (int)r.dmax, (int)t0, (int)(t0 + nt), k, splits,
+            split_stride, nt, pd, pi, s);
       if (e != hipSuccess) return e;
     }
     L += G;
@@ -548,19 +591,21 @@ hipError_t launch_window_band(const float* S, int64_t ldS, int64_t T, int L_min,
 hipError_t launch_merge(const double* part_d, const int32_t* part_i, int64_t T,
                         int L_min, int L_max, int k, int splits, int32_t* idx,
                         double* dist, hipStream_t s) {
-  return launch_merge_band(part_d, part_i, T, L_min, L_max, k, splits, 0, T - L_min + 1, idx,
-                           dist, s);
+  const int64_t np0 = T - L_min + 1;
+  const MergeSet a{part_d, part_i, splits, (int)np0}, none{nullptr, nullptr, 0, 0};
+  return launch_merge_band(a, none, T, L_min, L_max, k, 0, np0, 0, idx, dist, s);
 }
 
-hipError_t launch_merge_band(const double* part_d, const int32_t* part_i, int64_t T,
-                             int L_min, int L_max, int k, int splits, int64_t t0, int64_t nt,
+hipError_t launch_merge_band(const MergeSet& a, const MergeSet& b, int64_t T, int L_min,
+                             int L_max, int k, int64_t t0, int64_t nt, int64_t acc_end,
                              int32_t* idx, double* dist, hipStream_t s) {
   const int np0 = (int)(T - L_min + 1);
   const int NL = L_max - L_min + 1;
   const int64_t n = (int64_t)NL * nt;
-  hipLaunchKernelGGL(merge_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256),
-                     0, s, part_d, part_i, (int)T, np0, L_min, NL, k, splits, (int)t0,
-                     (int)nt, idx, dist);
+  if (n <= 0) return hipSuccess;
+  if (a.W > MERGE_MAX_SPLITS || b.W > MERGE_MAX_SPLITS) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(merge_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, b,
+                     (int)T, np0, L_min, NL, k, (int)t0, (int)nt, (int)acc_end, idx, dist);
   return hipGetLastError();
 }
 

@@ -95,15 +95,21 @@ def test_workspace_sizes():
 
 
 def test_band_workspace():
-    # band mode holds row_batch + L_max - 1 rows of S (not T), plus one extra
-    # zero tile of centred fields and norms
+    # band mode holds row_batch + L_max - 1 rows of S (not T) and the same band
+    # transposed (T rows of row_batch + L_max - 1, padded to 64), plus one extra
+    # zero tile of centred fields and norms and the column windows' lists
     T, D, L, k = 27394, 8192, 5, 10
     _, ws_full = _plan_code(T=T, D=D, L_min=L, L_max=L, k=k)
     rb = 4088
     _, ws_band = _plan_code(T=T, D=D, L_min=L, L_max=L, k=k, row_batch=rb)
-    ldS = (T + 63) // 64 * 64
-    assert ws_band < ws_full - (T - rb - L + 1) * ldS * 4 + 2 * (256 * D * 4 + 16 * 256 * 4)
-    assert ws_band >= (rb + L - 1) * ldS * 4 + (T + 255) // 256 * 256 * D * 4
+    def stride(n):  # whole 64-float segments, an odd number of them
+        m = (n + 63) // 64
+        return 64 * (m if m % 2 else m + 1)
+    ldS, ldST = stride(T), stride(rb + L - 1)
+    band = (rb + L - 1) * ldS * 4 + T * ldST * 4
+    lists = 16 * (T - L + 1) * k * 12
+    assert ws_band < ws_full - T * ldS * 4 + band + 2 * (256 * D * 4 + 16 * 256 * 4) + lists
+    assert ws_band >= band + (T + 255) // 256 * 256 * D * 4
     # T = 2^20: the whole matrix (4 TiB) does not fit one GPU, a band does
     _, ws_big = _plan_code(T=1 << 20, D=1024, L_min=L, L_max=L, k=k)
     _, ws_big_band = _plan_code(T=1 << 20, D=1024, L_min=L, L_max=L, k=k, row_batch=4088)

@@ -5,6 +5,7 @@ import os
 import subprocess
 import sys
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -34,6 +35,35 @@ def test_window_bytes():
     wb = bench.window_bytes(100, 5, rows=8)
     assert wb["algorithmic_bytes"] == 4.0 * 100 * 101 / 2
     assert wb["design_bytes"] == 4.0 * 100 * 100 * 12 / 8
+
+
+@pytest.mark.parametrize("T,L,rb", [(700, 4, 248), (700, 4, 8), (520, 16, 504), (1000, 2, 512),
+                                    (27394, 5, 4088)])
+def test_band_tiles(T, L, rb):
+    # brute force: pass t0 holds rows t0 .. t0 + srows - 1 in 256-row block-rows
+    # aligned to t0 and 256-column blocks aligned to 0; it contracts the tiles
+    # with an entry above the diagonal, and together the passes hold every
+    # entry (r, c), c > r, that a trajectory window reads
+    n, nb = T - L + 1, -(-T // 256)
+    tiles, covered = 0, np.zeros(T, bool)
+    for t0 in range(0, n, rb):
+        srows = min(min(rb, n - t0) + L - 1, T - t0)
+        nbi = -(-srows // 256)
+        for I in range(nbi):
+            r_lo = t0 + 256 * I
+            for J in range(nb):
+                if 256 * J + 255 > r_lo:  # some column above the tile's first row
+                    tiles += 1
+        if T <= 1000:
+            r = np.arange(t0, t0 + srows)[:, None]
+            c = np.arange(T)[None, :]
+            I, J = (r - t0) // 256, c // 256
+            # every entry above the diagonal in the pass's rows is in a
+            # contracted tile
+            assert np.all((J >= t0 // 256 + I) | (c <= r))
+            covered[t0:t0 + srows] = True
+    assert bench.band_tiles(T, L, L, rb) == tiles
+    assert T > 1000 or covered.all()
 
 
 @pytest.mark.parametrize("T,D,L,k,prec,rb", [

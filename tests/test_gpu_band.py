@@ -1,7 +1,10 @@
 """GPU parity of band mode (row-batched streaming of the distance matrix).
 
 With ``row_batch`` > 0 the library computes the matrix in bands of
-row_batch + L_max - 1 rows against all columns and never holds all of it. The
+row_batch + L_max - 1 rows against the later columns (only the tiles above the
+diagonal, kept as rows and transposed) and never holds all of it; each pass
+merges its rows' later candidates and every later row's candidates among its
+trajectories into running lists. The
 results must meet the same bar as the whole-matrix mode: the oracle's lists
 and scores within the precision's tolerance, on every row at small sizes and
 on sampled rows at large ones, for ragged passes (a last pass of one row, a
@@ -122,7 +125,7 @@ def test_band_full_workload():
 
 def test_band_beyond_device_memory():
     """T = 300000 fields of 32 x 32 (D = 1024), L = 5, k = 10: the whole
-    matrix needs more memory than the GPU has; band mode runs in ~21 GB."""
+    matrix needs more memory than the GPU has; band mode runs in ~38 GB."""
     from paper_2603_02059_amd import traknn as tk
     T, H, W, L, k, rb = 300000, 32, 32, 5, 10, 16376
     total = torch.cuda.get_device_properties(0).total_memory
