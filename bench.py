@@ -150,6 +150,46 @@ def time_sweep(tk, torch, X, w, steps, warmup, L_max=10):
     return out
 
 
+def time_small_d(tk, torch, synth, steps, warmup):
+    """The PCA-sized shape of the paper's trajectory-space study: T = 27394
+    fields of 4 x 8 (D = 32), L = 5, k = 40 (the largest k of its intrinsic-
+    dimension estimates), BF16x3; one call is knn plus the local dimension
+    for every k' <= k. The Gram is tiny here and the window/top-k stage
+    dominates."""
+    T, H, W, L, k = 27394, 4, 8, 5, 40
+    Xn, _ = synth.make_fields(T, H, W, sigma=1.0, n_events=20, event_len=L, seed=4)
+    X = torch.from_numpy(Xn).cuda()
+    p = tk.Plan(T, H * W, L, L, k, "bf16x3")
+    idx, dist = p.empty_outputs()
+    dims = torch.empty((p.NL, p.np0, k), dtype=torch.float64, device=X.device)
+    for _ in range(warmup):
+        p.knn(X, idx, dist)
+        p.local_dim(dist, dims)
+    torch.cuda.synchronize()
+    p.set_timing(True)
+    st = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        p.knn(X, idx, dist)
+        p.local_dim(dist, dims)
+        st.append(p.stage_times())
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    p.set_timing(False)
+    stage = {q: float(np.mean([s[q] for s in st])) for q in st[0]}
+    n = T - L + 1
+    win = window_bytes(T, L)
+    m = dims[0, :, [19, 29, 39]].nanmean(dim=0).cpu().numpy()
+    out = {"config": f"T={T}, {H}x{W} grid (D={H * W}), L={L}, k={k}, BF16x3, knn + local dimension",
+           "ms_per_call": ms, "pairs_per_s": float(n) * n / (ms * 1e-3), "stage_ms": stage,
+           "window_design_GBps": win["design_bytes"] / (stage["window_topk"] * 1e-3) / 1e9,
+           "mean_local_dim_k20_k30_k40": [float(v) for v in m]}
+    p.close()
+    del X
+    torch.cuda.empty_cache()
+    return out
+
+
 def time_backward(tk, torch, synth, steps):
     """The differentiation configuration: T = 10957 daily 64 x 128 fields,
     L = 5, k = 10, FP32 forward, then the backward of the summed score of the
@@ -357,6 +397,12 @@ def main():
         sweep = time_sweep(tk, torch, X, w, args.compare_steps, args.warmup)
         log(f"[bench] sweep: {sweep}")
 
+    small = None
+    if not args.only:
+        log("[bench] timing the small-D (PCA-sized) shape, k = 40, with the local dimension")
+        small = time_small_d(tk, torch, synth, args.compare_steps, args.warmup)
+        log(f"[bench] small D: {small}")
+
     bwd = None
     if not args.no_backward and not args.only:
         log("[bench] timing the backward configuration")
@@ -420,6 +466,7 @@ def main():
         "window_hbm": window_hbm,
         "band_mode": band,
         "sweep": sweep,
+        "small_d": small,
         "backward": bwd,
         "parity_sample": par,
         "planted_in_top40": f"{planted_found}/{len(starts)}",

@@ -74,6 +74,7 @@ def test_band_tiles(T, L, rb):
     (40000, 50400, 1, 1, "bf16x3", 0), (27000, 50400, 15, 1, "bf16x3", 0),
     (27000, 50400, 1, 50, "bf16x3", 0), (27000, 50625, 1, 1, "bf16x3", 0),
     (27394, 50861, 5, 10, "bf16x3", 0), (27394, 50861, 5, 10, "fp32", 0),
+    (27394, 32, 5, 40, "bf16x3", 0),
 ])
 def test_timed_shapes_plan(T, D, L, k, prec, rb):
     h, ws = tk.traknn_plan(T, D, L, L, k, prec, rb)

@@ -136,10 +136,12 @@ def test_all_lengths_sweep():
         assert np.array_equal(s[L - 1, :n], sL[0])
 
 
-def test_small_grid_full_length():
+@pytest.mark.parametrize("k", [10, 40])
+def test_small_grid_full_length(k):
     """A small-D shape (4 x 8 grid, D = 32, as after a PCA reduction) at the full
-    length: the Gram is tiny and the window/top-k stage dominates."""
-    T, L, k = 27394, 5, 10
+    length: the Gram is tiny and the window/top-k stage dominates. k = 40 is
+    the largest k of the paper's intrinsic-dimension estimates."""
+    T, L = 27394, 5
     _say(f"[gpu-full] small grid T={T} D=32 L={L} k={k}")
     Xn, starts = synth.make_fields(T, 4, 8, sigma=1.0, n_events=20, event_len=5, seed=4)
     idx, dist, s = _run(Xn, L, L, k, "bf16x3")
