@@ -28,6 +28,14 @@ constexpr int64_t WIN_TARGET_UNITS = TRAKNN_WIN_TARGET_UNITS;
 #define TRAKNN_BAND_WIN_TARGET_UNITS TRAKNN_WIN_TARGET_UNITS
 #endif
 constexpr int64_t BAND_WIN_TARGET_UNITS = TRAKNN_BAND_WIN_TARGET_UNITS;
+// Band mode's column windows have rows of only row_batch candidates, so each
+// wave's fixed costs (seeding its rows' lists, writing them out) weigh more:
+// half the waves per block. At T = 27394 with passes of 4088 rows this gives 2
+// waves per block, measured best against 1, 4 and 8.
+#ifndef TRAKNN_BAND_COL_TARGET_UNITS
+#define TRAKNN_BAND_COL_TARGET_UNITS 6144
+#endif
+constexpr int64_t BAND_COL_TARGET_UNITS = TRAKNN_BAND_COL_TARGET_UNITS;
 constexpr int MAX_SPLITS = MERGE_MAX_SPLITS;
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -77,7 +85,7 @@ bool plan_window(traknn_plan_s* p) {
   const int64_t rows = p->rb && p->rb < p->np0 ? p->rb : p->np0;
   const int64_t target = p->rb ? BAND_WIN_TARGET_UNITS : WIN_TARGET_UNITS;
   p->win_splits = window_splits(p, rows, p->np0, target);
-  p->col_splits = p->rb ? window_splits(p, p->np0, rows, target) : 0;
+  p->col_splits = p->rb ? window_splits(p, p->np0, rows, BAND_COL_TARGET_UNITS) : 0;
   return p->win_splits > 0 && (!p->rb || p->col_splits > 0);
 }
 
