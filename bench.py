@@ -32,6 +32,7 @@ import numpy as np  # noqa: E402
 PEAKS_TFLOPS = {"bf16x3": 2516.6, "fp16": 2516.6, "fp32": 157.3}  # dense MFMA
 HBM_PEAK_GBS = 8000.0
 GRAM_SOURCES = ("paper_2603_02059_amd/csrc/gram.hip",)
+WINDOW_SOURCES = ("paper_2603_02059_amd/csrc/window_topk.hip",)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gram_bf16x3_T27394_D8192_traffic.txt")
 
 
@@ -39,28 +40,52 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def gram_source_hash() -> str:
+def source_hash(paths=GRAM_SOURCES) -> str:
     h = hashlib.sha256()
-    for p in GRAM_SOURCES:
+    for p in paths:
         with open(os.path.join(ROOT, p), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def read_traffic():
-    """HBM bytes per Gram launch from the committed rocprofv3 counter summary,
-    or None if absent or taken on a different Gram kernel source."""
+def gram_source_hash() -> str:
+    return source_hash(GRAM_SOURCES)
+
+
+def read_traffic_file() -> dict:
+    kv = {}
     try:
-        kv = {}
         with open(TRAFFIC_FILE) as f:
             for line in f:
                 if ":" in line and not line.startswith("#"):
                     a, b = line.split(":", 1)
                     kv[a.strip()] = b.strip()
+    except OSError:
+        pass
+    return kv
+
+
+def read_traffic():
+    """HBM bytes per Gram launch from the committed rocprofv3 counter summary,
+    or None if absent or taken on a different Gram kernel source."""
+    kv = read_traffic_file()
+    try:
         if kv.get("gram_source_sha256_16") != gram_source_hash():
             return None
         return float(kv["hbm_bytes_per_launch"])
-    except (OSError, KeyError, ValueError):
+    except (KeyError, ValueError):
+        return None
+
+
+def read_window_traffic():
+    """HBM bytes (read + written) per single-length window launch from the same
+    summary, or None if absent or taken on a different window kernel source."""
+    kv = read_traffic_file()
+    try:
+        if kv.get("window_source_sha256_16") != source_hash(WINDOW_SOURCES):
+            return None
+        return float(kv["window1_read_bytes"]) + float(kv["window1_write_bytes"])
+    except (KeyError, ValueError):
         return None
 
 
@@ -429,9 +454,12 @@ def main():
     traffic = read_traffic() if hp == "bf16x3" and w.name == "full" else None
     wb = window_bytes(w.T, w.L)
     win_ms = head["stage_ms"]["window_topk"]
+    wt = read_window_traffic() if hp == "bf16x3" and w.name == "full" else None
     window_hbm = {"kernel": f"window1_kernel<{w.L}, 1>", "avg_launch_ms": win_ms,
                   "algorithmic_GBps": wb["algorithmic_bytes"] / (win_ms * 1e-3) / 1e9,
                   "design_GBps": wb["design_bytes"] / (win_ms * 1e-3) / 1e9,
+                  "counter_bytes": wt,
+                  "counter_GBps": wt / (win_ms * 1e-3) / 1e9 if wt else None,
                   "peak_GBps": HBM_PEAK_GBS, **wb}
     line = {
         "metric": "trajectory pairs/sec at T=27394,D=8192,L=5,k=10; Gram MFMA util vs FP32 path",
