@@ -80,6 +80,7 @@ def check_rows(X, L: int, k: int, rows, gidx, gdist, gscore, tol: float,
     gscore = np.asarray(gscore, dtype=np.float64)
     max_d_err = 0.0
     max_s_err = 0.0
+    d_errs, s_errs = [], []
     set_diff_rows = 0
     for r, t in enumerate(rows):
         gi = gidx[r]
@@ -96,6 +97,7 @@ def check_rows(X, L: int, k: int, rows, gidx, gdist, gscore, tol: float,
         scale = np.maximum(np.abs(od), 1e-300)
         derr = np.where(od == 0, np.abs(gdist[r]), aerr / scale)
         max_d_err = max(max_d_err, float(derr.max()))
+        d_errs.append(derr)
         assert np.all(aerr <= allow), (f"row {t}: distance error {derr.max():.3e} "
                                        f"beyond tolerance (tol {tol}, norm_tol {norm_tol})")
         if set(gi.tolist()) != set(ridx[r].tolist()):
@@ -120,7 +122,10 @@ def check_rows(X, L: int, k: int, rows, gidx, gdist, gscore, tol: float,
         else:
             serr = abs(gscore[r] - rscore[r]) / abs(rscore[r])
         max_s_err = max(max_s_err, float(serr))
+        s_errs.append(serr)
         assert abs(gscore[r] - rscore[r]) <= sallow or serr <= tol, (
             f"row {t}: score error {serr:.3e} beyond tolerance")
     return {"max_dist_rel_err": max_d_err, "max_score_rel_err": max_s_err,
+            "p99_dist_rel_err": float(np.percentile(np.concatenate(d_errs), 99)) if d_errs else 0.0,
+            "p99_score_rel_err": float(np.percentile(s_errs, 99)) if s_errs else 0.0,
             "set_diff_rows": set_diff_rows, "rows": len(rows)}
