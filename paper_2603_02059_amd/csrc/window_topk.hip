@@ -406,14 +406,24 @@ hipError_t launch_win1(const float* S, int64_t ldS, int T, int s0, int s_end, in
   return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void merge_kernel(
+// One thread per (length, row): a k-step merge of the sorted partial lists
+// (at most MS of them) and, for the rows below acc_end, the running list
+// already in the output. Each source's current head stays in registers (the
+// source loops are unrolled over MS) and only the source that advanced is
+// read again; the running list is first copied to LDS, since the output that
+// holds it is overwritten while it is merged.
+constexpr int MERGE_THREADS = 64;
+template <int MS>
+__global__ __launch_bounds__(MERGE_THREADS) void merge_kernel(
     MergeSet a, MergeSet b, int T, int np0, int Lmin, int NL, int k, int t0, int nt,
     int acc_end, int32_t* __restrict__ idx, double* __restrict__ dist) {
   // rows t0 .. t0 + nt - 1 of every length. A set's partial lists are indexed
-  // from t0 and cover its first rows only; for the rows below acc_end the list
-  // already in the output (a running list of earlier launches, empty slots as
-  // index -1) is one more sorted source.
-  const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  // from t0 and cover its first rows only; empty slots of the running list
+  // are index -1.
+  extern __shared__ __attribute__((aligned(16))) char msm[];
+  double* rd = (double*)msm + (size_t)threadIdx.x * k;                          // [64][k]
+  int* ri = (int*)((double*)msm + (size_t)MERGE_THREADS * k) + (size_t)threadIdx.x * k;
+  const int64_t g = (int64_t)blockIdx.x * MERGE_THREADS + threadIdx.x;
   if (g >= (int64_t)NL * nt) return;
   const int li = (int)(g / nt);
   const int tr = (int)(g % nt);
@@ -428,43 +438,57 @@ __global__ __launch_bounds__(256) void merge_kernel(
     }
     return;
   }
-  double rd[TRAKNN_MAX_K];
-  int ri[TRAKNN_MAX_K];
   const int nr = t < acc_end ? k : 0;
   for (int q = 0; q < nr; ++q) {
     rd[q] = od[q];
     ri[q] = oi[q] < 0 ? INT_MAX : oi[q];
   }
   const int wa = tr < a.nt ? a.W : 0, wb = tr < b.nt ? b.W : 0;
-  const int ns = wa + wb;  // partial-list sources
-  int pos[2 * MERGE_MAX_SPLITS];
-  for (int w = 0; w < ns; ++w) pos[w] = 0;
+  const int ns = wa + wb;  // partial-list sources: a's splits, then b's
+  // entry p of source w's list
+  auto at = [&](int w, int p, double& d, int& i) __attribute__((always_inline)) {
+    const bool in_a = w < wa;
+    const int64_t o = (((int64_t)(in_a ? w : w - wa) * NL + li) * (in_a ? a.nt : b.nt) + tr) * k + p;
+    d = in_a ? a.d[o] : b.d[o];
+    i = in_a ? a.i[o] : b.i[o];
+  };
+  // source w's current head is (hd[w], hi[w]), entry pos[w] of its list
+  int pos[MS];
+  double hd[MS];
+  int hi[MS];
+#pragma unroll
+  for (int w = 0; w < MS; ++w) {
+    pos[w] = 0;
+    hd[w] = __builtin_huge_val();
+    hi[w] = INT_MAX;
+    if (w < ns) at(w, 0, hd[w], hi[w]);
+  }
   int rpos = 0;
   for (int q = 0; q < k; ++q) {
-    int best = -1;  // source: a partial list w, or ns for the running list
-    double bd = 0.0;
-    int bi = INT_MAX;
-    if (rpos < nr) {
-      best = ns;
-      bd = rd[rpos];
-      bi = ri[rpos];
-    }
-    for (int w = 0; w < ns; ++w) {
-      if (pos[w] >= k) continue;
-      const bool in_a = w < wa;
-      const MergeSet& m = in_a ? a : b;
-      const int ws = in_a ? w : w - wa;
-      const int64_t o = (((int64_t)ws * NL + li) * m.nt + tr) * k + pos[w];
-      const double d = m.d[o];
-      const int i = m.i[o];
-      if (best < 0 || key_less(d, i, bd, bi)) {
+    int best = MS;  // MS: the running list
+    double bd = rpos < nr ? rd[rpos] : __builtin_huge_val();
+    int bi = rpos < nr ? ri[rpos] : INT_MAX;
+    bool have = rpos < nr;
+#pragma unroll
+    for (int w = 0; w < MS; ++w) {
+      if (w < ns && pos[w] < k && (!have || key_less(hd[w], hi[w], bd, bi))) {
         best = w;
-        bd = d;
-        bi = i;
+        bd = hd[w];
+        bi = hi[w];
+        have = true;
       }
     }
-    if (best == ns) rpos++;
-    else pos[best]++;
+    if (best == MS) {
+      rpos++;
+    } else {
+#pragma unroll
+      for (int w = 0; w < MS; ++w) {
+        if (w == best) {
+          pos[w]++;
+          if (pos[w] < k) at(w, pos[w], hd[w], hi[w]);
+        }
+      }
+    }
     oi[q] = bi == INT_MAX ? -1 : bi;
     od[q] = bd;
   }
@@ -604,8 +628,17 @@ hipError_t launch_merge_band(const MergeSet& a, const MergeSet& b, int64_t T, in
   const int64_t n = (int64_t)NL * nt;
   if (n <= 0) return hipSuccess;
   if (a.W > MERGE_MAX_SPLITS || b.W > MERGE_MAX_SPLITS) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(merge_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, b,
-                     (int)T, np0, L_min, NL, k, (int)t0, (int)nt, (int)acc_end, idx, dist);
+  const int ns = a.W + b.W;
+  const dim3 grid((unsigned)((n + MERGE_THREADS - 1) / MERGE_THREADS));
+  const size_t lds = (size_t)MERGE_THREADS * k * (sizeof(double) + sizeof(int));
+#define TRAKNN_MERGE_LAUNCH(MS)                                                              \
+  hipLaunchKernelGGL(merge_kernel<MS>, grid, dim3(MERGE_THREADS), lds, s, a, b, (int)T, np0, \
+                     L_min, NL, k, (int)t0, (int)nt, (int)acc_end, idx, dist)
+  if (ns <= 4) TRAKNN_MERGE_LAUNCH(4);
+  else if (ns <= 8) TRAKNN_MERGE_LAUNCH(8);
+  else if (ns <= 16) TRAKNN_MERGE_LAUNCH(16);
+  else TRAKNN_MERGE_LAUNCH(2 * MERGE_MAX_SPLITS);
+#undef TRAKNN_MERGE_LAUNCH
   return hipGetLastError();
 }
 
