@@ -68,10 +68,12 @@ int window_splits(const traknn_plan_s* p, int64_t rows, int64_t cands, int64_t t
   const size_t base = window1_lds_bytes(L, G, k, 0);
   const size_t per_wave = window1_lds_bytes(L, G, k, 1) - base;
   if (base + per_wave > MAX_WIN_LDS) return 0;
-  // Every wave keeps its own k-long lists, so for k above 10 the target
-  // shrinks in proportion: at T = 27394 this gives 4, 2 and 1 waves per block
-  // for k = 10, 20 and 40, the fastest of the counts measured for each.
-  if (k > 10) target = target * 10 / k;
+  // Every wave keeps its own k-long list per row and length of its pass, so
+  // when those hold more than 10 entries (G k > 10) the target shrinks in
+  // proportion. At T = 27394 this gives 4, 2 and 1 waves per block for k =
+  // 10, 20 and 40 at one length, and 2 for a sweep's pairs of lengths at
+  // k = 10: the fastest of the counts measured for each.
+  if (G * k > 10) target = target * 10 / (G * k);
   int64_t W = (target + nrb - 1) / nrb;
   const int64_t wmax = (int64_t)((MAX_WIN_LDS - base) / per_wave);
   if (W > wmax) W = wmax;
