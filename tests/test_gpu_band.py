@@ -62,6 +62,8 @@ def _check_all_rows(idx, dist, s, L):
     (520, 300, 16, 64, "bf16x3", 504),   # 2 passes, the second of one row
     (512, 128, 5, 10, "bf16x3", 1 << 16),  # one pass over all rows
     (300, 5, 2, 9, "fp32", 40),
+    (257, 64, 2, 3, "bf16x3", 248),   # T one field past a tile: two passes
+    (600, 50, 16, 5, "fp32", 8),      # 8-row passes with 23-row bands
 ])
 def test_band_parity(T, D, L, k, prec, rb):
     _say(f"[gpu-band] T={T} D={D} L={L} k={k} prec={prec} row_batch={rb}")
@@ -77,10 +79,14 @@ def test_band_parity(T, D, L, k, prec, rb):
     _check_all_rows(idx[0], dist[0], s[0], L)
 
 
-def test_band_multi_length_sweep():
-    T, D, Lmax, k, rb = 600, 200, 6, 5, 96
+@pytest.mark.parametrize("T,H,W,Lmax,k,rb", [
+    (600, 10, 20, 6, 5, 96),
+    (260, 4, 10, 16, 3, 8),   # lengths 1..16 in 8-row passes
+])
+def test_band_multi_length_sweep(T, H, W, Lmax, k, rb):
+    D = H * W
     _say(f"[gpu-band] sweep L=1..{Lmax} T={T} D={D} row_batch={rb}")
-    Xn, _ = synth.make_fields(T, 10, 20, sigma=2.0, n_events=3, event_len=4, seed=5)
+    Xn, _ = synth.make_fields(T, H, W, sigma=2.0, n_events=3, event_len=4, seed=5)
     idx, dist, s = _run(Xn, 1, k, "bf16x3", rb, L_max=Lmax)
     S = oracle.snapshot_dist(Xn)
     for L in range(1, Lmax + 1):
