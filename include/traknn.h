@@ -105,10 +105,12 @@ extern "C" {
  *               Gram work is that of the whole-matrix mode plus about one
  *               diagonal tile per 256-row block-row of each pass, and the
  *               workspace holds (row_batch + L_max - 1) rows of the matrix
- *               plus T rows of row_batch + L_max - 1 entries. Results agree
- *               with the whole-matrix mode within the precision's rounding
- *               (the band's tiles are aligned to its first row, not to
- *               multiples of 256). */
+ *               plus T rows of row_batch + L_max - 1 entries. Each distance
+ *               above the diagonal comes from the same operands in the same
+ *               order as in the whole-matrix mode, so whenever the window
+ *               sums are exact (FP32 distances whose exponents span fewer
+ *               than about 29 bits, as for field data) the results equal the
+ *               whole-matrix mode's bit for bit, for any row_batch. */
 typedef struct {
   int64_t T;
   int64_t D;

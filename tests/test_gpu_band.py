@@ -5,7 +5,9 @@ row_batch + L_max - 1 rows against the later columns (only the tiles above the
 diagonal, kept as rows and transposed) and never holds all of it; each pass
 merges its rows' later candidates and every later row's candidates among its
 trajectories into running lists. The
-results must meet the same bar as the whole-matrix mode: the oracle's lists
+results must equal the whole-matrix mode's bit for bit (every distance above
+the diagonal comes from the same operands in the same order, and the window
+sums of these inputs are exact) and meet its bar against the oracle: the oracle's lists
 and scores within the precision's tolerance, on every row at small sizes and
 on sampled rows at large ones, for ragged passes (a last pass of one row, a
 band that spans a partial 256-row block-row, passes of 8 rows, one pass
@@ -40,6 +42,16 @@ def _run(Xn, L, k, prec, row_batch, L_max=None):
     del X
     torch.cuda.empty_cache()
     return out
+
+
+def _assert_same_as_whole_matrix(Xn, L, L_max, k, prec, band):
+    """Band mode computes every distance above the diagonal from the same
+    operands in the same order as the whole-matrix mode, and the window sums
+    of these inputs are exact, so its lists, distances and scores are the
+    whole-matrix mode's bit for bit."""
+    whole = _run(Xn, L, k, prec, 0, L_max=L_max)
+    for name, u, v in zip(("indices", "distances", "scores"), band, whole):
+        assert np.array_equal(u, v, equal_nan=True), f"{name} differ from the whole-matrix mode"
 
 
 def _check_all_rows(idx, dist, s, L):
@@ -77,6 +89,7 @@ def test_band_parity(T, D, L, k, prec, rb):
                        norm_tol=gram_norm_tol(prec, D))
     _say(f"  {stats}")
     _check_all_rows(idx[0], dist[0], s[0], L)
+    _assert_same_as_whole_matrix(Xn, L, L, k, prec, (idx, dist, s))
 
 
 @pytest.mark.parametrize("T,H,W,Lmax,k,rb", [
@@ -99,12 +112,14 @@ def test_band_multi_length_sweep(T, H, W, Lmax, k, rb):
         _say(f"  L={L}: {stats}")
         assert np.all(idx[L - 1, n:] == -1) and np.all(np.isinf(dist[L - 1, n:]))
         assert np.all(np.isnan(s[L - 1, n:]))
+    _assert_same_as_whole_matrix(Xn, 1, Lmax, k, "bf16x3", (idx, dist, s))
 
 
 def test_band_full_workload():
     """T = 27394 daily 64 x 128 fields, L = 5, k = 10, BF16x3, passes of 4088
     rows (4092-row bands, 16 block-rows each): every row's list is valid,
-    sampled rows match the oracle, and the scores match the whole-matrix mode."""
+    sampled rows match the oracle, and the lists, distances and scores equal
+    the whole-matrix mode's bit for bit."""
     w = synth.WORKLOADS["full"]
     rb = 4088
     _say(f"[gpu-band] full T={w.T} D={w.D} L={w.L} k={w.k} row_batch={rb}")
@@ -122,11 +137,10 @@ def test_band_full_workload():
     stats = check_rows(Xn, w.L, w.k, rows, idx[rows], dist[rows], s[rows],
                        precision_tol("bf16x3"))
     _say(f"  {stats}")
-    # the whole-matrix mode: both within 1e-5 of the oracle, so within 2e-5
+    # the whole-matrix mode's results, bit for bit
     iw, dw, sw = _run(Xn, w.L, w.k, "bf16x3", 0)
-    np.testing.assert_allclose(s, sw[0], rtol=2e-5)
-    same = np.mean(np.all(np.sort(idx, 1) == np.sort(iw[0], 1), axis=1))
-    _say(f"  rows with the whole-matrix mode's neighbour set: {same:.5f}")
+    assert np.array_equal(idx, iw[0]) and np.array_equal(dist, dw[0])
+    assert np.array_equal(s, sw[0])
 
 
 def test_band_beyond_device_memory():
