@@ -205,6 +205,24 @@ def test_prefix_scores_every_k():
         np.testing.assert_allclose(sp[0, :, kk - 1], ref, rtol=1e-5)
 
 
+@pytest.mark.parametrize("T,H,W", [(3000, 8, 16), (27394, 4, 8)])
+def test_lists_independent_of_waves_per_block(T, H, W):
+    """The planner gives k = 10, 20 and 40 different numbers of waves per
+    8-row block (4, 2 and 1 at T = 27394), so their searches split each row's
+    diagonals differently. The k nearest are the first k of the 2k nearest
+    in (distance, index) order and the window sums are exact, so the first 10
+    entries of every k = 20 and k = 40 list equal the k = 10 list bit for
+    bit."""
+    L = 5
+    _say(f"[gpu] list prefixes across k = 10, 20, 40 at T={T} D={H * W}")
+    Xn, _ = synth.make_fields(T, H, W, sigma=1.0, n_events=3, event_len=L, seed=T)
+    i10, d10, _ = _run(Xn, L, 10, "bf16x3")
+    for k in (20, 40):
+        ik, dk, _ = _run(Xn, L, k, "bf16x3")
+        assert np.array_equal(ik[..., :10], i10), f"k={k}: indices differ from k=10"
+        assert np.array_equal(dk[..., :10], d10), f"k={k}: distances differ from k=10"
+
+
 def test_determinism():
     w = synth.WORKLOADS["tiny"]
     _say("[gpu] determinism")
