@@ -122,6 +122,35 @@ def traknn_plan_destroy(plan) -> None:
     _ck(_lib.traknn_plan_destroy(plan), "traknn_plan_destroy")
 
 
+def workspace_bytes(T: int, D: int, L_min: int, L_max: int, k: int,
+                    precision: int | str = TRAKNN_BF16X3, row_batch: int = 0) -> int:
+    """Workspace of a plan, from the planner alone (no GPU involved)."""
+    h, ws = traknn_plan(T, D, L_min, L_max, k, precision, row_batch)
+    traknn_plan_destroy(h)
+    return ws
+
+
+def row_batch_for(T: int, D: int, L_min: int, L_max: int, k: int,
+                  precision: int | str = TRAKNN_BF16X3, *, max_bytes: int) -> int:
+    """A row_batch whose workspace fits in max_bytes: 0 (the whole matrix, the
+    faster mode) when that fits, else the largest multiple of 8 a bisection
+    finds. Band mode's workspace grows with row_batch (both stored copies of
+    the band do), up to a wobble of the window's partial lists of a few MB.
+    Raises ValueError if even passes of 8 rows do not fit."""
+    if workspace_bytes(T, D, L_min, L_max, k, precision, 0) <= max_bytes:
+        return 0
+    if workspace_bytes(T, D, L_min, L_max, k, precision, 8) > max_bytes:
+        raise ValueError(f"no row_batch fits a workspace of {max_bytes} bytes")
+    lo, hi = 1, (T - L_min + 1 + 7) // 8  # in units of 8 rows; lo fits
+    while lo < hi:
+        mid = (lo + hi + 1) // 2
+        if workspace_bytes(T, D, L_min, L_max, k, precision, 8 * mid) <= max_bytes:
+            lo = mid
+        else:
+            hi = mid - 1
+    return 8 * lo
+
+
 def traknn_knn(plan, X, ldx: int, ws, ws_bytes: int, nbr_idx, nbr_dist,
                stream=None) -> None:
     _ck(_lib.traknn_knn(plan, _ptr(X), int(ldx), _ptr(ws), int(ws_bytes),

@@ -194,3 +194,22 @@ def test_plain_c_client(tmp_path):
     r = subprocess.run([exe], capture_output=True, text=True, timeout=60)
     assert r.returncode == 0, r.stderr
     assert "c abi ok" in r.stdout
+
+
+def test_row_batch_for_a_memory_budget():
+    """The helper picks the whole matrix when it fits, else a row_batch whose
+    workspace fits the budget while one 64 rows larger does not."""
+    T, D, L, k = 27394, 8192, 5, 10
+    whole = tk.workspace_bytes(T, D, L, L, k)
+    assert tk.row_batch_for(T, D, L, L, k, max_bytes=whole) == 0
+    for budget in (1 << 30, 2 << 30, 3 << 30):
+        rb = tk.row_batch_for(T, D, L, L, k, max_bytes=budget)
+        assert rb > 0 and rb % 8 == 0
+        assert tk.workspace_bytes(T, D, L, L, k, row_batch=rb) <= budget
+        if rb + 64 < T - L + 1:
+            assert tk.workspace_bytes(T, D, L, L, k, row_batch=rb + 64) > budget
+    # the out-of-core case: 300000 fields of 1024 cells in 40 GiB
+    rb = tk.row_batch_for(300000, 1024, L, L, k, max_bytes=40 << 30)
+    assert rb >= 16376
+    with pytest.raises(ValueError):
+        tk.row_batch_for(T, D, L, L, k, max_bytes=1 << 20)
