@@ -407,7 +407,9 @@ def main():
         band = {"row_batch": rb, "ms_per_step": r["ms_per_step"],
                 "pairs_per_s": pairs / (r["ms_per_step"] * 1e-3),
                 "passes_ms": r["stage_ms"]["gram"],
-                "mfma_work_vs_whole_matrix": flops / gram_flops(w.T, w.D, "bf16x3"),
+                "mfma_work_vs_algorithmic": flops / gram_flops(w.T, w.D, "bf16x3"),
+                "gram_tiles_vs_whole_matrix":
+                    band_tiles(w.T, w.L, w.L, rb) / (-(-w.T // 256) * (-(-w.T // 256) + 1) / 2),
                 "workspace_GiB": r["ws_bytes"] / 2 ** 30,
                 "whole_matrix_workspace_GiB": results.get("bf16x3", r)["ws_bytes"] / 2 ** 30}
         if "bf16x3" in results:
