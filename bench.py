@@ -11,9 +11,9 @@ The headline path is the split BF16x3 Gram; the plain FP32 and single-pass
 FP16 paths are timed beside it. One JSON line goes to stdout; progress to
 stderr.
 
-``--scaling`` instead times the shapes of the paper's scaling study (Section
-4, Fig. 1: defaults T = 27000 random fields of 180 x 280, d = 1, k = 1, then
-one parameter swept at a time) and prints one JSON line per shape.
+``--scaling`` instead times the default shape of the paper's scaling study
+(Section 4: T = 27000 random fields of 180 x 280, d = 1, k = 1) as context
+and prints one JSON line per precision.
 """
 from __future__ import annotations
 
@@ -170,9 +170,42 @@ def time_sweep(tk, torch, X, w, steps, warmup, L_max=10):
     ms = 1e3 * (time.perf_counter() - t0) / steps
     p.set_timing(False)
     out = {"lengths": f"1..{L_max}", "ms_per_call": ms,
-           "stage_ms": {k: float(np.mean([s[k] for s in st])) for k in st[0]}}
+           "stage_ms": {k: float(np.mean([s[k] for s in st])) for k in st[0]},
+           "idx": idx, "dist": dist, "scores": scores}
     p.close()
     return out
+
+
+def sweep_parity(Xn, w, sweep, L_max, nrows, starts):
+    """Per-length agreement of the sweep with the oracle on the same sampled
+    rows for every L = 1..L_max (evenly spaced, plus the planted starts), all
+    lengths from one oracle pass over X: set differences (admitted only at
+    oracle gaps below 1e-5), maximum distance and score errors."""
+    import oracle
+    from tests.parity import check_rows
+
+    n_last = w.T - L_max + 1
+    rows = set(np.linspace(0, n_last - 1, nrows).astype(int).tolist())
+    rows |= {s for s in starts if s < n_last}
+    rows = np.array(sorted(rows), dtype=np.int64)
+    t0 = time.perf_counter()
+    refs = oracle.knn_rows_multi(Xn, L_max, w.k, rows)
+    el = time.perf_counter() - t0
+    gi = sweep["idx"].cpu().numpy()
+    gd = sweep["dist"].cpu().numpy()
+    gs = sweep["scores"].cpu().numpy()
+    per_L = []
+    for L in range(1, L_max + 1):
+        try:
+            st = check_rows(Xn, L, w.k, rows, gi[L - 1][rows], gd[L - 1][rows],
+                            gs[L - 1][rows], 1e-5, ref=refs[L - 1], label=f"bench sweep L={L}")
+            ok = True
+        except AssertionError as e:  # reported, not hidden
+            st, ok = {"error": str(e)[:200]}, False
+        per_L.append({"L": L, "pass": ok, "rows": int(rows.size),
+                      **{k: st.get(k) for k in ("set_diff_rows", "max_dist_rel_err",
+                                                "max_score_rel_err")}})
+    return {"rows_per_L": int(rows.size), "oracle_s": el, "per_L": per_L}
 
 
 def time_small_d(tk, torch, synth, steps, warmup):
@@ -245,6 +278,18 @@ def time_backward(tk, torch, synth, steps):
     return out
 
 
+def cpu_model() -> str | None:
+    """The host CPU's model name as /proc/cpuinfo reports it."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(Xn, w, budget_s, gidx, gdist, gscore):
     """The FP64 oracle on evenly spaced sample rows, timed on the host cores,
     plus the parity of the GPU rows against it."""
@@ -277,6 +322,8 @@ def cpu_baseline(Xn, w, budget_s, gidx, gdist, gscore):
         "value": len(rows) * n / el,
         "unit": "pairs/s",
         "cores": threads,
+        "nproc": os.cpu_count(),
+        "cpu_model": cpu_model(),
         "kind": "oracle",
         "sample": f"{len(rows)} evenly spaced rows x {n} candidates each of the same "
                   f"workload (FP64 direct differences, direct L-sums, sorted top-k), "
@@ -285,26 +332,15 @@ def cpu_baseline(Xn, w, budget_s, gidx, gdist, gscore):
 
 
 def scaling(tk, torch, steps, warmup):
-    """Time the scaling study's shapes (Section 4, Fig. 1) on random fields
-    (the paper evaluates on synthetic random data): the defaults, then the
-    grid side h (w = h), the number of fields T, the length d and k swept one
-    at a time. BF16x3; the defaults also in FP32."""
-    base = {"T": 27000, "h": 180, "w": 280, "d": 1, "k": 1}
-    shapes = [dict(base, prec="bf16x3"), dict(base, prec="fp32")]
-    shapes += [dict(base, h=h, w=h, prec="bf16x3") for h in (45, 90, 135, 225)]
-    shapes += [dict(base, T=T, prec="bf16x3") for T in (5000, 10000, 20000, 40000)]
-    shapes += [dict(base, d=d, prec="bf16x3") for d in (2, 5, 10, 15)]
-    shapes += [dict(base, k=k, prec="bf16x3") for k in (5, 10, 20, 50)]
-    # the case study's scale (Section 5): 75 years of daily 181 x 281 fields,
-    # d = 5, k = 10
-    shapes += [{"T": 27394, "h": 181, "w": 281, "d": 5, "k": 10, "prec": p}
-               for p in ("bf16x3", "fp32")]
+    """Time the default shape of the paper's scaling study (Section 4: T =
+    27000 random fields of 180 x 280, d = 1, k = 1; the paper evaluates on
+    random data) in BF16x3 and FP32, as context only."""
+    T, D, L, k = 27000, 180 * 280, 1, 1
     gen = torch.Generator(device="cuda")
-    for sh in shapes:
-        T, D, L, k = sh["T"], sh["h"] * sh["w"], sh["d"], sh["k"]
+    for prec in ("bf16x3", "fp32"):
         gen.manual_seed(T * 7 + D)
         X = torch.randn((T, D), generator=gen, device="cuda", dtype=torch.float32)
-        p = tk.Plan(T, D, L, L, k, sh["prec"])
+        p = tk.Plan(T, D, L, L, k, prec)
         idx, dist = p.empty_outputs()
         scores = torch.empty((1, p.np0), dtype=torch.float64, device="cuda")
         for _ in range(warmup):
@@ -318,7 +354,8 @@ def scaling(tk, torch, steps, warmup):
         torch.cuda.synchronize()
         ms = 1e3 * (time.perf_counter() - t0) / steps
         n = T - L + 1
-        line = {"shape": sh, "D": D, "ms_per_call": ms, "pairs_per_s": n * n / (ms * 1e-3),
+        line = {"shape": {"T": T, "h": 180, "w": 280, "d": L, "k": k, "prec": prec},
+                "D": D, "ms_per_call": ms, "pairs_per_s": n * n / (ms * 1e-3),
                 "workspace_GiB": p.ws_bytes / 2 ** 30}
         print(json.dumps(line), flush=True)
         p.close()
@@ -337,6 +374,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0,
                     help="seconds of oracle time for the CPU baseline (0 = skip)")
     ap.add_argument("--only", default=None, help="time one precision only")
+    ap.add_argument("--sweep-rows", type=int, default=64,
+                    help="oracle rows per length checked for the all-lengths sweep (0 = skip)")
     ap.add_argument("--no-backward", action="store_true",
                     help="skip the backward timing (T = 10957 configuration)")
     ap.add_argument("--scaling", action="store_true",
@@ -422,6 +461,11 @@ def main():
     if not args.only:
         log("[bench] timing the all-lengths sweep L=1..10")
         sweep = time_sweep(tk, torch, X, w, args.compare_steps, args.warmup)
+        if args.sweep_rows > 0:
+            log(f"[bench] sweep parity: {args.sweep_rows} oracle rows per length")
+            sweep["parity"] = sweep_parity(Xn, w, sweep, 10, args.sweep_rows, starts)
+        for key in ("idx", "dist", "scores"):
+            sweep.pop(key)
         log(f"[bench] sweep: {sweep}")
 
     small = None

@@ -76,11 +76,40 @@ extern "C" {
 #define TRAKNN_FP32 0
 #define TRAKNN_BF16X3 1
 #define TRAKNN_FP16 2
+/*   TRAKNN_FP64   : fused mode only. Eq. 4 with FP64 operands (the FP32 fields
+ *                   shifted per cell by the FP64 sample mean), FP64 products
+ *                   and sums on the vector ALUs, distances then rounded to
+ *                   FP32 as the other modes store them. For the small grids
+ *                   of the paper's PCA comparison (13 to 33 components), where
+ *                   the contraction is too shallow for MFMA to pay and a
+ *                   reduced-precision Gram loses accuracy to cancellation. */
+#define TRAKNN_FP64 3
+
+/* Modes (traknn_config.mode).
+ *   TRAKNN_MODE_MATRIX : the distance matrix is materialised, whole or in bands
+ *                        (row_batch), and a window pass reads it.
+ *   TRAKNN_MODE_FUSED  : S-free. Each tile of the upper triangle (tiles overlap
+ *                        by L - 1 fields, so every trajectory pair of a tile has
+ *                        its L terms inside it) forms its trajectory distances
+ *                        in LDS and offers every pair to both of its rows; only
+ *                        candidates within a row's bound reach HBM. The bound of
+ *                        each row is the k-th distance over a first launch on a
+ *                        band of tiles that gives every row a few hundred
+ *                        candidates, and the final k come from a select over
+ *                        the rest. A row whose buffer of candidates overflows
+ *                        (many candidates tied at its bound) is recomputed
+ *                        exactly in FP64 from the fields. Single length only
+ *                        (L_min == L_max), row_batch 0; precisions FP64 (vector
+ *                        FP64 tiles of 128 fields) and FP32 / BF16X3 / FP16
+ *                        (the MFMA Gram of 256 fields with the walk in its
+ *                        epilogue). */
+#define TRAKNN_MODE_MATRIX 0
+#define TRAKNN_MODE_FUSED 1
 
 #define TRAKNN_MAX_L 16
 #define TRAKNN_MAX_K 64
 
-/* Problem description.
+/* Problem description (set unused fields to 0).
  *   T, D        number of fields (time steps) and cells per field, >= 1.
  *   L_min,L_max trajectory lengths, 1 <= L_min <= L_max <= TRAKNN_MAX_L. One
  *               call emits neighbour lists for every L in [L_min, L_max]
@@ -88,7 +117,8 @@ extern "C" {
  *               L_min == 1.
  *   k           neighbours per trajectory, 1 <= k <= TRAKNN_MAX_K; every length
  *               must leave each row k candidates: T - L_max + 1 >= k + 2 L_max - 1.
- *   precision   TRAKNN_FP32, TRAKNN_BF16X3 or TRAKNN_FP16.
+ *   precision   TRAKNN_FP32, TRAKNN_BF16X3 or TRAKNN_FP16; TRAKNN_FP64 in
+ *               fused mode.
  *   row_batch   0: the whole T x T distance matrix is held in the workspace
  *               (about 4 T^2 bytes) and only its upper-triangular tiles are
  *               contracted. > 0, a multiple of 8: band mode (row-batched
@@ -110,7 +140,9 @@ extern "C" {
  *               order as in the whole-matrix mode, so whenever the window
  *               sums are exact (FP32 distances whose exponents span fewer
  *               than about 29 bits, as for field data) the results equal the
- *               whole-matrix mode's bit for bit, for any row_batch. */
+ *               whole-matrix mode's bit for bit, for any row_batch.
+ *   mode        TRAKNN_MODE_MATRIX (0) or TRAKNN_MODE_FUSED (1), above.
+ *   reserved    0. */
 typedef struct {
   int64_t T;
   int64_t D;
@@ -119,6 +151,8 @@ typedef struct {
   int32_t k;
   int32_t precision;
   int64_t row_batch;
+  int32_t mode;      /* TRAKNN_MODE_MATRIX or TRAKNN_MODE_FUSED */
+  int32_t reserved;  /* must be 0 */
 } traknn_config;
 
 typedef struct traknn_plan_s* traknn_plan_t;
@@ -210,12 +244,22 @@ int traknn_local_dim(traknn_plan_t plan, const double* nbr_dist, double* out, vo
  *   grad_scores [in]  FP64 [T-L+1] upstream weights w_t.
  *   grad_X      [out] FP32 T x D, row stride ldg (ldg >= D); every row written
  *                     (zeros where no term touches it).
- *   workspace   [in]  as for traknn_knn.
+ *   workspace   [in]  256-byte aligned scratch of at least the bytes
+ *                     traknn_backward_workspace reports (the traknn_knn
+ *                     workspace always suffices); overwritten.
  * Errors: INVALID_ARG, WORKSPACE, HIP; UNSUPPORTED if L_min != L_max. */
 int traknn_score_backward(traknn_plan_t plan, const float* X, int64_t ldx,
                           const int32_t* nbr_idx, const double* grad_scores,
                           float* grad_X, int64_t ldg, void* workspace,
                           size_t workspace_bytes, void* stream);
+
+/* Device bytes traknn_score_backward needs: the layout puts its scratch at
+ * the start of the workspace, so a buffer of this size (or the whole
+ * traknn_knn workspace, which is never smaller) serves it. Lets a caller free
+ * the forward workspace between the forward and the backward pass.
+ *   bytes [out] the size, at most workspace_bytes of traknn_plan.
+ * Errors: INVALID_ARG for NULL. */
+int traknn_backward_workspace(traknn_plan_t plan, size_t* bytes);
 
 /* Static description of a status code; never NULL. */
 const char* traknn_status_string(int status);

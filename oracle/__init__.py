@@ -61,6 +61,8 @@ def _load():
             lib.oracle_snapshot_dist.argtypes = [_f64p, i64, i64, _f64p]
             lib.oracle_traj_dist_from_snapshot.argtypes = [_f64p, i64, i32, _f64p]
             lib.oracle_traj_dist_rows.argtypes = [_f64p, i64, i64, i32, _i64p, i64, _f64p]
+            lib.oracle_traj_dist_rows_multi.argtypes = [_f64p, i64, i64, i32, _i64p, i64,
+                                                        _f64p]
             lib.oracle_pair_traj_dist.argtypes = [_f64p, i64, i64, i32, _i64p, _i64p, i64, _f64p]
             lib.oracle_knn_rows.argtypes = [_f64p, _i64p, i64, i64, i32, i32, _i32p,
                                             _f64p, _f64p, _f64p]
@@ -68,7 +70,8 @@ def _load():
             lib.oracle_local_dim.argtypes = [_f64p, i64, i32, _f64p]
             lib.oracle_num_threads.argtypes = []
             for f in (lib.oracle_snapshot_dist, lib.oracle_traj_dist_from_snapshot,
-                      lib.oracle_traj_dist_rows, lib.oracle_pair_traj_dist,
+                      lib.oracle_traj_dist_rows, lib.oracle_traj_dist_rows_multi,
+                      lib.oracle_pair_traj_dist,
                       lib.oracle_knn_rows, lib.oracle_score_grad, lib.oracle_local_dim,
                       lib.oracle_num_threads):
                 f.restype = ctypes.c_int
@@ -131,6 +134,32 @@ def traj_dist_rows(X, L: int, rows) -> np.ndarray:
     out = np.empty((rows.size, T - L + 1), dtype=np.float64)
     _check(_load().oracle_traj_dist_rows(X, T, D, int(L), rows, rows.size, out),
            "traj_dist_rows")
+    return out
+
+
+def traj_dist_rows_multi(X, L_max: int, rows) -> np.ndarray:
+    """Rows D_L(t, :) for every L = 1..L_max, straight from X: [L_max, r, T],
+    entry [L-1, r, j] = D_L(rows[r], j) for j < T - L + 1, +inf beyond."""
+    X = _x64(X)
+    T, D = X.shape
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    out = np.empty((L_max, rows.size, T), dtype=np.float64)
+    _check(_load().oracle_traj_dist_rows_multi(X, T, D, int(L_max), rows, rows.size, out),
+           "traj_dist_rows_multi")
+    return out
+
+
+def knn_rows_multi(X, L_max: int, k: int, rows):
+    """Sampled rows of every length L = 1..L_max from one pass over X: a list
+    whose entry L - 1 is (idx, dist, score, gap, drows) as knn_rows returns
+    them for length L (rows must exist for L_max)."""
+    allrows = traj_dist_rows_multi(X, L_max, rows)
+    T = allrows.shape[2]
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    out = []
+    for L in range(1, L_max + 1):
+        drows = np.ascontiguousarray(allrows[L - 1, :, :T - L + 1])
+        out.append(knn_from_rows(drows, rows, L, k) + (drows,))
     return out
 
 

@@ -111,6 +111,37 @@ int oracle_traj_dist_rows(const double* X, int64_t T, int64_t D, int L,
   return ORACLE_OK;
 }
 
+/* Rows of every trajectory length L = 1..L_max at once, straight from X:
+ *   out[((L-1)*nrows + r)*n'_1 + j] = D_L(rows[r], j)  for j in [0, T-L+1),
+ * +inf for j >= T-L+1 (no such trajectory), with n'_1 = T. Each D_L is the
+ * direct sum of Eq. 2 over m = 0..L-1 in increasing m, so carrying the
+ * partial sum from L - 1 to L performs exactly the additions of a fresh
+ * direct sum; the snapshot distances are direct differences. Every row
+ * needs rows[r] + L_max <= T. */
+int oracle_traj_dist_rows_multi(const double* X, int64_t T, int64_t D, int L_max,
+                                const int64_t* rows, int64_t nrows, double* out) {
+  if (!X || !rows || !out || L_max < 1 || L_max > T || D < 1) return ORACLE_EINVAL;
+  for (int64_t r = 0; r < nrows; ++r)
+    if (rows[r] < 0 || rows[r] + L_max > T) return ORACLE_EINVAL;
+  for (int64_t r = 0; r < nrows; ++r) {
+    int64_t t = rows[r];
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < T; ++j) {
+      double s = 0.0;
+      for (int L = 1; L <= L_max; ++L) {
+        double* o = out + ((int64_t)(L - 1) * nrows + r) * T + j;
+        if (j + L > T) {
+          *o = INFINITY;
+          continue;
+        }
+        s += snap_dist(X, D, t + L - 1, j + L - 1);
+        *o = s;
+      }
+    }
+  }
+  return ORACLE_OK;
+}
+
 /* Distances of explicit trajectory pairs (ti[q], tj[q]). */
 int oracle_pair_traj_dist(const double* X, int64_t T, int64_t D, int L,
                           const int64_t* ti, const int64_t* tj, int64_t npairs,

@@ -95,6 +95,49 @@ bool plan_window(traknn_plan_s* p) {
   return p->win_splits > 0 && (!p->rb || p->col_splits > 0);
 }
 
+// Fused mode: tile stride, block-rows and the establishing offsets (the
+// diagonal band of tiles plus far offsets, as many as keep the establishing
+// launch within about one round of the GPU: every row then meets a few
+// hundred candidates there), and the per-row candidate capacity.
+void plan_fused(traknn_plan_s* p) {
+  const traknn_config& c = p->cfg;
+  FusedGeom& g = p->fg;
+  const bool f64 = c.precision == TRAKNN_FP64;
+  const int tile = f64 ? FUSED_F64_TILE : GRAM_TILE;
+  g.T = (int)c.T;
+  g.np = (int)p->np0;
+  g.L = c.L_max;
+  g.k = c.k;
+  g.B = tile - (c.L_max - 1);
+  if (!f64) g.B = g.B / 4 * 4;  // 16-byte aligned chunk-norm loads of each panel
+  g.nbt = (int)((g.np + g.B - 1) / g.B);
+  const int64_t round = f64 ? 2 * 256 : 256;  // tiles the GPU runs at once
+  g.nh = 0;
+  g.h[g.nh++] = 0;
+  int64_t count = g.nbt;
+  if (g.nbt <= 4) {
+    for (int h = 1; h < g.nbt; ++h) g.h[g.nh++] = h;
+  } else {
+    const int num[7] = {1, 1, 3, 1, 3, 5, 7}, den[7] = {2, 4, 4, 8, 8, 8, 8};
+    for (int u = 0; u < 7 && g.nh < FUSED_MAX_OFFSETS; ++u) {
+      const int h = (int)(((int64_t)g.nbt * num[u] + den[u] - 1) / den[u]);
+      bool dup = h < 1 || h >= g.nbt;
+      for (int q = 0; q < g.nh && !dup; ++q) dup = g.h[q] == h;
+      if (dup || count + (g.nbt - h) > round) continue;
+      g.h[g.nh++] = h;
+      count += g.nbt - h;
+    }
+  }
+  for (int q = g.nh; q < FUSED_MAX_OFFSETS; ++q) g.h[q] = -1;
+  // the MFMA tiles read a full 256-row panel from every block-row's start
+  if (!f64) {
+    const int64_t need = (int64_t)(g.nbt - 1) * g.B + GRAM_TILE;
+    if (need > p->Tpad) p->Tpad = round_up(need, GRAM_TILE);
+  }
+  const int64_t cap = (int64_t)c.k * 64 > 1024 ? (int64_t)c.k * 64 : 1024;
+  p->fcap = (int)(cap < p->np0 ? cap : p->np0);
+}
+
 void plan_layout(traknn_plan_s* p) {
   Layout& L = p->lay;
   size_t o = 0;
@@ -104,8 +147,27 @@ void plan_layout(traknn_plan_s* p) {
     return at;
   };
   const int prec = p->cfg.precision;
+  const size_t np = (size_t)(p->T - p->cfg.L_min + 1);
+  L.bw_zero = take((2 * np + (size_t)p->T) * sizeof(int32_t));
+  L.bw_ptr = take((np + 1) * sizeof(int32_t));
+  L.bw_rev = take(np * p->cfg.k * sizeof(int32_t));
+  L.bw_end = o;
   L.mu_part = take((size_t)p->tchunks * p->D * sizeof(double));
   L.mu = take((size_t)p->D * sizeof(double));
+  if (p->fused) {
+    // S-free: the centred operands of the MFMA tiles (none for the FP64 tiles,
+    // which read the fields) and the per-row candidate buffers
+    const bool mfma = prec != TRAKNN_FP64;
+    L.ncs = take(mfma ? (size_t)norm_chunks(p->Dpad) * p->Tpad * sizeof(float) : 0);
+    L.xc = take(mfma ? (size_t)p->Tpad * p->Dpad * elem_bytes(prec) : 0);
+    L.f_bound = take(np * sizeof(double));
+    L.f_cnt = take(np * sizeof(int32_t));
+    L.f_bd = take(np * (size_t)p->fcap * sizeof(double));
+    L.f_bi = take(np * (size_t)p->fcap * sizeof(int32_t));
+    L.S = L.ST = L.part_d = L.part_i = L.cpart_d = L.cpart_i = o;
+    L.total = o;
+    return;
+  }
   L.ncs = take((size_t)norm_chunks(p->Dpad) * p->Tpad * sizeof(float));
   L.xc = take((size_t)p->Tpad * p->Dpad * elem_bytes(prec));
   L.S = take((size_t)(p->rb ? p->band_rows : p->T) * p->ldS * sizeof(float));
@@ -120,11 +182,6 @@ void plan_layout(traknn_plan_s* p) {
   const size_t ncol = p->rb ? (size_t)p->col_splits * p->NL * p->np0 * p->cfg.k : 0;
   L.cpart_d = take(ncol * sizeof(double));
   L.cpart_i = take(ncol * sizeof(int32_t));
-  const size_t np = (size_t)(p->T - p->cfg.L_min + 1);
-  L.bw_cnt = take(np * sizeof(int32_t));
-  L.bw_ptr = take((np + 1) * sizeof(int32_t));
-  L.bw_fill = take(np * sizeof(int32_t));
-  L.bw_rev = take(np * p->cfg.k * sizeof(int32_t));
   L.total = o;
 }
 
@@ -134,9 +191,8 @@ int check_x(const traknn_plan_s* p, const float* X, int64_t ldx) {
   return TRAKNN_OK;
 }
 
-int check_ws(const traknn_plan_s* p, const void* ws, size_t bytes) {
-  if (!ws || !aligned(ws, WS_ALIGN) || bytes < p->lay.total)
-    return TRAKNN_ERR_WORKSPACE;
+int check_ws(const void* ws, size_t bytes, size_t need) {
+  if (!ws || !aligned(ws, WS_ALIGN) || bytes < need) return TRAKNN_ERR_WORKSPACE;
   return TRAKNN_OK;
 }
 
@@ -152,126 +208,56 @@ int record(traknn_plan_s* p, int slot, hipStream_t s) {
 
 }  // namespace
 
-extern "C" {
+namespace {
 
-const char* traknn_status_string(int status) {
-  switch (status) {
-    case TRAKNN_OK:
-      return "ok";
-    case TRAKNN_ERR_INVALID_ARG:
-      return "invalid argument";
-    case TRAKNN_ERR_UNSUPPORTED:
-      return "unsupported configuration";
-    case TRAKNN_ERR_WORKSPACE:
-      return "workspace missing, misaligned or too small";
-    case TRAKNN_ERR_HIP:
-      return "HIP runtime or kernel launch failure";
-    default:
-      return "unknown status";
-  }
-}
-
-int traknn_plan(const traknn_config* cfg, traknn_plan_t* out,
-                size_t* workspace_bytes) {
-  if (!cfg || !out || !workspace_bytes) return TRAKNN_ERR_INVALID_ARG;
-  *out = nullptr;
-  const traknn_config c = *cfg;
-  if (c.T < 1 || c.T > MAX_T || c.D < 1 || c.D > MAX_D)
-    return TRAKNN_ERR_INVALID_ARG;
-  if (c.L_min < 1 || c.L_max < c.L_min || c.L_max > TRAKNN_MAX_L)
-    return TRAKNN_ERR_INVALID_ARG;
-  if (c.k < 1 || c.k > TRAKNN_MAX_K) return TRAKNN_ERR_INVALID_ARG;
-  if (c.precision != TRAKNN_FP32 && c.precision != TRAKNN_BF16X3 &&
-      c.precision != TRAKNN_FP16)
-    return TRAKNN_ERR_INVALID_ARG;
-  // every row of every length needs k candidates outside its exclusion zone
-  if (c.T - c.L_max + 1 < (int64_t)c.k + 2 * c.L_max - 1)
-    return TRAKNN_ERR_INVALID_ARG;
-  // band mode: passes start on multiples of 8 rows (16-byte aligned norm loads)
-  if (c.row_batch < 0 || c.row_batch % 8 != 0) return TRAKNN_ERR_INVALID_ARG;
-  if (c.L_min != c.L_max && c.L_min != 1) return TRAKNN_ERR_UNSUPPORTED;
-  // the Gram stage addresses a 256-field operand panel with 32-bit offsets
-  if ((uint64_t)round_up(c.D, stage_k(c.precision)) * elem_bytes(c.precision) * GRAM_TILE >
-      0x7FFFFFFFull)
-    return TRAKNN_ERR_UNSUPPORTED;
-
-  traknn_plan_s* p = new (std::nothrow) traknn_plan_s();
-  if (!p) return TRAKNN_ERR_INVALID_ARG;
-  p->cfg = c;
-  p->T = c.T;
-  p->D = c.D;
-  p->Dpad = round_up(c.D, stage_k(c.precision));
-  p->rb = c.row_batch;
-  // a band's last block-row may reach one tile past the last field
-  p->Tpad = round_up(c.T, GRAM_TILE) + (p->rb ? GRAM_TILE : 0);
-  p->ldS = matrix_stride(c.T);
-  p->np0 = c.T - c.L_min + 1;
-  p->NL = c.L_max - c.L_min + 1;
-  p->nb = (int)((c.T + GRAM_TILE - 1) / GRAM_TILE);
-  p->ntiles = (int64_t)p->nb * (p->nb + 1) / 2;
-  p->band_rows = p->rb + c.L_max - 1 < c.T ? p->rb + c.L_max - 1 : c.T;
-  p->ldST = p->rb ? matrix_stride(p->band_rows) : 0;
-  p->tchunks = colstat_chunks(c.T);
-  if (!plan_window(p)) {
-    delete p;
-    return TRAKNN_ERR_UNSUPPORTED;
-  }
-  plan_layout(p);
-  *out = p;
-  *workspace_bytes = p->lay.total;
-  return TRAKNN_OK;
-}
-
-int traknn_plan_destroy(traknn_plan_t plan) {
-  if (!plan) return TRAKNN_ERR_INVALID_ARG;
-  if (plan->events_ready)
-    for (int i = 0; i <= NUM_STAGES; ++i) (void)hipEventDestroy(plan->ev[i]);
-  delete plan;
-  return TRAKNN_OK;
-}
-
-int traknn_set_timing(traknn_plan_t plan, int enable) {
-  if (!plan) return TRAKNN_ERR_INVALID_ARG;
-  if (enable && !plan->events_ready) {
-    for (int i = 0; i <= NUM_STAGES; ++i) {
-      if (hipEventCreate(&plan->ev[i]) != hipSuccess) {
-        for (int q = 0; q < i; ++q) (void)hipEventDestroy(plan->ev[q]);
-        return TRAKNN_ERR_HIP;
-      }
-    }
-    plan->events_ready = 1;
-  }
-  plan->timing = enable ? 1 : 0;
-  plan->timed_calls = 0;
-  return TRAKNN_OK;
-}
-
-int traknn_stage_times(traknn_plan_t plan, double* ms, int max_stages,
-                       int* n_stages) {
-  if (!plan || !ms || !n_stages || max_stages < 1) return TRAKNN_ERR_INVALID_ARG;
-  if (!plan->events_ready || plan->timed_calls == 0) return TRAKNN_ERR_UNSUPPORTED;
-  if (hipEventSynchronize(plan->ev[NUM_STAGES]) != hipSuccess) return TRAKNN_ERR_HIP;
-  const int n = max_stages < NUM_STAGES ? max_stages : NUM_STAGES;
-  for (int i = 0; i < n; ++i) {
-    float t = 0.f;
-    if (hipEventElapsedTime(&t, plan->ev[i], plan->ev[i + 1]) != hipSuccess)
-      return TRAKNN_ERR_HIP;
-    ms[i] = (double)t;
-  }
-  *n_stages = n;
-  return TRAKNN_OK;
-}
-
-int traknn_knn(traknn_plan_t plan, const float* X, int64_t ldx, void* workspace,
-               size_t workspace_bytes, int32_t* nbr_idx, double* nbr_dist,
-               void* stream) {
-  if (!plan || !nbr_idx || !nbr_dist) return TRAKNN_ERR_INVALID_ARG;
-  int rc = check_x(plan, X, ldx);
-  if (rc) return rc;
-  rc = check_ws(plan, workspace, workspace_bytes);
-  if (rc) return rc;
+// Fused mode after the centring: the establishing launch, each row's bound,
+// the filtering launch, then the select (and the exact recomputation of rows
+// whose candidate buffers overflowed). Timing slots: 3 after the fused tiles
+// and bounds, 4 after the select, 5 after the fallback.
+int enqueue_fused(traknn_plan_s* plan, const float* X, int64_t ldx, void* workspace,
+                  int32_t* nbr_idx, double* nbr_dist, hipStream_t s) {
   const traknn_config& c = plan->cfg;
-  hipStream_t s = (hipStream_t)stream;
+  const Layout& L = plan->lay;
+  const FusedGeom& g = plan->fg;
+  const double* mu = at<double>(workspace, L.mu);
+  double* bound = at<double>(workspace, L.f_bound);
+  const FusedOut out{at<int32_t>(workspace, L.f_cnt), at<double>(workspace, L.f_bd),
+                     at<int32_t>(workspace, L.f_bi), plan->fcap};
+  const int D = (int)plan->D;
+  int rc;
+  if ((rc = fail_hip(launch_fused_clear(g, out, s)))) return rc;
+  if (c.precision == TRAKNN_FP64) {
+    if ((rc = fail_hip(launch_fused_f64(X, ldx, D, mu, g, true, bound, out, s)))) return rc;
+    if ((rc = fail_hip(launch_fused_bound(g, out, bound, s)))) return rc;
+    if ((rc = fail_hip(launch_fused_f64(X, ldx, D, mu, g, false, bound, out, s)))) return rc;
+  } else {
+    const void* xc = at<char>(workspace, L.xc);
+    const float* ncs = at<float>(workspace, L.ncs);
+    if ((rc = fail_hip(launch_gram_fused(xc, ncs, plan->T, plan->Tpad, plan->Dpad, c.precision,
+                                         g, true, bound, out, s))))
+      return rc;
+    if ((rc = fail_hip(launch_fused_bound(g, out, bound, s)))) return rc;
+    if ((rc = fail_hip(launch_gram_fused(xc, ncs, plan->T, plan->Tpad, plan->Dpad, c.precision,
+                                         g, false, bound, out, s))))
+      return rc;
+  }
+  if ((rc = record(plan, 3, s))) return rc;
+  if ((rc = fail_hip(launch_fused_select(X, ldx, D, mu, g, out, nbr_idx, nbr_dist, s))))
+    return rc;
+  if ((rc = record(plan, 4, s))) return rc;
+  if ((rc = record(plan, 5, s))) return rc;
+  if (plan->timing) plan->timed_calls++;
+  return TRAKNN_OK;
+}
+
+// The launch sequence of traknn_knn on validated arguments: workspace is at
+// least plan->lay.total bytes, 256-byte aligned. Nothing it reads from the
+// workspace is read before this call has written it, so the workspace needs
+// no clearing between calls.
+int enqueue_knn(traknn_plan_s* plan, const float* X, int64_t ldx, void* workspace,
+                int32_t* nbr_idx, double* nbr_dist, hipStream_t s) {
+  int rc;
+  const traknn_config& c = plan->cfg;
   const Layout& L = plan->lay;
   double* mu_part = at<double>(workspace, L.mu_part);
   double* mu = at<double>(workspace, L.mu);
@@ -286,11 +272,13 @@ int traknn_knn(traknn_plan_t plan, const float* X, int64_t ldx, void* workspace,
                                      mu_part, mu, s))))
     return rc;
   if ((rc = record(plan, 1, s))) return rc;
-  if ((rc = fail_hip(launch_centre_convert(X, ldx, plan->T, plan->D, plan->Tpad,
+  if (c.precision != TRAKNN_FP64 &&
+      (rc = fail_hip(launch_centre_convert(X, ldx, plan->T, plan->D, plan->Tpad,
                                            plan->Dpad, c.precision, mu, xc,
                                            ncs, s))))
     return rc;
   if ((rc = record(plan, 2, s))) return rc;
+  if (plan->fused) return enqueue_fused(plan, X, ldx, workspace, nbr_idx, nbr_dist, s);
   if (plan->rb) {
     // Band mode (row-batched streaming). Pass p owns the trajectories t0 ..
     // t1 - 1; its band is the rows of S they reach, against the columns from
@@ -362,6 +350,139 @@ int traknn_knn(traknn_plan_t plan, const float* X, int64_t ldx, void* workspace,
   return TRAKNN_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+const char* traknn_status_string(int status) {
+  switch (status) {
+    case TRAKNN_OK:
+      return "ok";
+    case TRAKNN_ERR_INVALID_ARG:
+      return "invalid argument";
+    case TRAKNN_ERR_UNSUPPORTED:
+      return "unsupported configuration";
+    case TRAKNN_ERR_WORKSPACE:
+      return "workspace missing, misaligned or too small";
+    case TRAKNN_ERR_HIP:
+      return "HIP runtime or kernel launch failure";
+    default:
+      return "unknown status";
+  }
+}
+
+int traknn_plan(const traknn_config* cfg, traknn_plan_t* out,
+                size_t* workspace_bytes) {
+  if (!cfg || !out || !workspace_bytes) return TRAKNN_ERR_INVALID_ARG;
+  *out = nullptr;
+  const traknn_config c = *cfg;
+  if (c.T < 1 || c.T > MAX_T || c.D < 1 || c.D > MAX_D)
+    return TRAKNN_ERR_INVALID_ARG;
+  if (c.L_min < 1 || c.L_max < c.L_min || c.L_max > TRAKNN_MAX_L)
+    return TRAKNN_ERR_INVALID_ARG;
+  if (c.k < 1 || c.k > TRAKNN_MAX_K) return TRAKNN_ERR_INVALID_ARG;
+  if (c.precision != TRAKNN_FP32 && c.precision != TRAKNN_BF16X3 &&
+      c.precision != TRAKNN_FP16 && c.precision != TRAKNN_FP64)
+    return TRAKNN_ERR_INVALID_ARG;
+  if ((c.mode != TRAKNN_MODE_MATRIX && c.mode != TRAKNN_MODE_FUSED) || c.reserved != 0)
+    return TRAKNN_ERR_INVALID_ARG;
+  const bool fused = c.mode == TRAKNN_MODE_FUSED;
+  // fused mode: one length, no bands; FP64 only there
+  if (fused && c.row_batch != 0) return TRAKNN_ERR_INVALID_ARG;
+  if (fused && c.L_min != c.L_max) return TRAKNN_ERR_UNSUPPORTED;
+  if (!fused && c.precision == TRAKNN_FP64) return TRAKNN_ERR_UNSUPPORTED;
+  // every row of every length needs k candidates outside its exclusion zone
+  if (c.T - c.L_max + 1 < (int64_t)c.k + 2 * c.L_max - 1)
+    return TRAKNN_ERR_INVALID_ARG;
+  // band mode: passes start on multiples of 8 rows (16-byte aligned norm loads)
+  if (c.row_batch < 0 || c.row_batch % 8 != 0) return TRAKNN_ERR_INVALID_ARG;
+  if (c.L_min != c.L_max && c.L_min != 1) return TRAKNN_ERR_UNSUPPORTED;
+  // the Gram stage addresses a 256-field operand panel with 32-bit offsets
+  if ((uint64_t)round_up(c.D, stage_k(c.precision)) * elem_bytes(c.precision) * GRAM_TILE >
+      0x7FFFFFFFull)
+    return TRAKNN_ERR_UNSUPPORTED;
+
+  traknn_plan_s* p = new (std::nothrow) traknn_plan_s();
+  if (!p) return TRAKNN_ERR_INVALID_ARG;
+  p->cfg = c;
+  p->T = c.T;
+  p->D = c.D;
+  p->Dpad = round_up(c.D, stage_k(c.precision));
+  p->rb = c.row_batch;
+  // a band's last block-row may reach one tile past the last field
+  p->Tpad = round_up(c.T, GRAM_TILE) + (p->rb ? GRAM_TILE : 0);
+  p->ldS = matrix_stride(c.T);
+  p->np0 = c.T - c.L_min + 1;
+  p->NL = c.L_max - c.L_min + 1;
+  p->nb = (int)((c.T + GRAM_TILE - 1) / GRAM_TILE);
+  p->ntiles = (int64_t)p->nb * (p->nb + 1) / 2;
+  p->band_rows = p->rb + c.L_max - 1 < c.T ? p->rb + c.L_max - 1 : c.T;
+  p->ldST = p->rb ? matrix_stride(p->band_rows) : 0;
+  p->tchunks = colstat_chunks(c.T);
+  p->fused = fused ? 1 : 0;
+  if (fused) {
+    plan_fused(p);
+  } else if (!plan_window(p)) {
+    delete p;
+    return TRAKNN_ERR_UNSUPPORTED;
+  }
+  plan_layout(p);
+  *out = p;
+  *workspace_bytes = p->lay.total;
+  return TRAKNN_OK;
+}
+
+int traknn_plan_destroy(traknn_plan_t plan) {
+  if (!plan) return TRAKNN_ERR_INVALID_ARG;
+  if (plan->events_ready)
+    for (int i = 0; i <= NUM_STAGES; ++i) (void)hipEventDestroy(plan->ev[i]);
+  delete plan;
+  return TRAKNN_OK;
+}
+
+int traknn_set_timing(traknn_plan_t plan, int enable) {
+  if (!plan) return TRAKNN_ERR_INVALID_ARG;
+  if (enable && !plan->events_ready) {
+    for (int i = 0; i <= NUM_STAGES; ++i) {
+      if (hipEventCreate(&plan->ev[i]) != hipSuccess) {
+        for (int q = 0; q < i; ++q) (void)hipEventDestroy(plan->ev[q]);
+        return TRAKNN_ERR_HIP;
+      }
+    }
+    plan->events_ready = 1;
+  }
+  plan->timing = enable ? 1 : 0;
+  plan->timed_calls = 0;
+  return TRAKNN_OK;
+}
+
+int traknn_stage_times(traknn_plan_t plan, double* ms, int max_stages,
+                       int* n_stages) {
+  if (!plan || !ms || !n_stages || max_stages < 1) return TRAKNN_ERR_INVALID_ARG;
+  if (!plan->events_ready || plan->timed_calls == 0) return TRAKNN_ERR_UNSUPPORTED;
+  if (hipEventSynchronize(plan->ev[NUM_STAGES]) != hipSuccess) return TRAKNN_ERR_HIP;
+  const int n = max_stages < NUM_STAGES ? max_stages : NUM_STAGES;
+  for (int i = 0; i < n; ++i) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, plan->ev[i], plan->ev[i + 1]) != hipSuccess)
+      return TRAKNN_ERR_HIP;
+    ms[i] = (double)t;
+  }
+  *n_stages = n;
+  return TRAKNN_OK;
+}
+
+int traknn_knn(traknn_plan_t plan, const float* X, int64_t ldx, void* workspace,
+               size_t workspace_bytes, int32_t* nbr_idx, double* nbr_dist,
+               void* stream) {
+  if (!plan || !nbr_idx || !nbr_dist) return TRAKNN_ERR_INVALID_ARG;
+  int rc = check_x(plan, X, ldx);
+  if (rc) return rc;
+  rc = check_ws(workspace, workspace_bytes, plan->lay.total);
+  if (rc) return rc;
+  return enqueue_knn(plan, X, ldx, workspace, nbr_idx, nbr_dist, (hipStream_t)stream);
+}
+
 int traknn_score(traknn_plan_t plan, const double* nbr_dist, double* scores,
                  void* stream) {
   if (!plan || !nbr_dist || !scores) return TRAKNN_ERR_INVALID_ARG;
@@ -393,16 +514,21 @@ int traknn_score_backward(traknn_plan_t plan, const float* X, int64_t ldx,
   int rc = check_x(plan, X, ldx);
   if (rc) return rc;
   if (ldg < plan->D) return TRAKNN_ERR_INVALID_ARG;
-  rc = check_ws(plan, workspace, workspace_bytes);
+  rc = check_ws(workspace, workspace_bytes, plan->lay.bw_end);
   if (rc) return rc;
   const traknn_config& c = plan->cfg;
   if (c.L_min != c.L_max) return TRAKNN_ERR_UNSUPPORTED;
   const Layout& L = plan->lay;
   return fail_hip(launch_backward(
       X, ldx, plan->T, plan->D, c.L_max, c.k, nbr_idx, grad_scores, grad_X, ldg,
-      at<int32_t>(workspace, L.bw_cnt), at<int32_t>(workspace, L.bw_ptr),
-      at<int32_t>(workspace, L.bw_fill), at<int32_t>(workspace, L.bw_rev),
-      (hipStream_t)stream));
+      at<int32_t>(workspace, L.bw_zero), at<int32_t>(workspace, L.bw_ptr),
+      at<int32_t>(workspace, L.bw_rev), (hipStream_t)stream));
+}
+
+int traknn_backward_workspace(traknn_plan_t plan, size_t* bytes) {
+  if (!plan || !bytes) return TRAKNN_ERR_INVALID_ARG;
+  *bytes = plan->lay.bw_end;
+  return TRAKNN_OK;
 }
 
 }  // extern "C"

@@ -23,15 +23,23 @@ __global__ __launch_bounds__(256) void fill_i32_kernel(int32_t* p, int64_t n,
   if (i < n) p[i] = v;
 }
 
+// Reverse-list counts, plus the rows any term touches: a = t + m (the rows
+// of a weighted trajectory) and a = j + m (those of its neighbours), m < L.
+// Flags are plain stores of 1, so concurrent writers agree.
 __global__ __launch_bounds__(256) void rev_count_kernel(
     const int32_t* __restrict__ idx, const double* __restrict__ w, int np,
-    int k, int32_t* __restrict__ cnt) {
+    int k, int L, int32_t* __restrict__ cnt, int32_t* __restrict__ touch) {
   const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (g >= (int64_t)np * k) return;
   const int t = (int)(g / k);
   if (w[t] == 0.0) return;
   const int j = idx[g];
-  if (j >= 0 && j < np) atomicAdd(&cnt[j], 1);
+  if (j < 0 || j >= np) return;
+  atomicAdd(&cnt[j], 1);
+  for (int m = 0; m < L; ++m) {
+    touch[t + m] = 1;
+    touch[j + m] = 1;
+  }
 }
 
 // Exclusive scan of cnt[0..n) into ptr[0..n], one workgroup of 1024 threads.
@@ -91,111 +99,134 @@ __global__ __launch_bounds__(256) void rev_sort_kernel(const int32_t* __restrict
   }
 }
 
-// Columns per thread: a workgroup gathers one output row over 256 * GCOLS
-// columns, and a second grid dimension covers the rest of the row, so a row's
-// terms are gathered by several workgroups at once (the gather is latency
-// bound: each term is one dependent source-row read).
-constexpr int GCOLS = 4;
+// A workgroup owns GB_COLS columns of one output row: each of its 256
+// threads holds GB_VEC groups of 4 consecutive columns, loaded and stored as
+// 16-byte vectors (strided rows fall back to scalar stores of the output).
+// Rows that no term touches are written as zeros and nothing else; touched
+// rows gather their terms with every term's GB_VEC source vectors in flight
+// at once, in FP64, rounded once to FP32.
+constexpr int GB_VEC = 4;
+constexpr int GB_COLS = 256 * 4 * GB_VEC;
 
-// Does output row a receive any term?
-__device__ __forceinline__ bool row_has_terms(int a, int np, int L, const double* w,
-                                              const int32_t* ptr) {
-  for (int m = 0; m < L; ++m) {
-    const int t = a - m;
-    if (t >= 0 && t < np && (w[t] != 0.0 || ptr[t + 1] > ptr[t])) return true;
-  }
-  return false;
-}
-
+template <bool VEC_OUT>
 __global__ __launch_bounds__(256) void grad_rows_kernel(
     const float* __restrict__ X, int64_t ldx, int T, int64_t D, int L, int k,
     const int32_t* __restrict__ idx, const double* __restrict__ w,
     const int32_t* __restrict__ ptr, const int32_t* __restrict__ rev,
-    float* __restrict__ g, int64_t ldg) {
+    const int32_t* __restrict__ touch, float* __restrict__ g, int64_t ldg) {
   const int a = blockIdx.x;
   const int np = T - L + 1;
-  const int64_t c0 = (int64_t)blockIdx.y * 256 * GCOLS;
+  const int64_t cbase = (int64_t)blockIdx.y * GB_COLS + 4 * threadIdx.x;
   float* ga = g + (int64_t)a * ldg;
-  if (!row_has_terms(a, np, L, w, ptr)) {  // untouched row: zeros
-#pragma unroll
-    for (int e = 0; e < GCOLS; ++e) {
-      const int64_t p = c0 + threadIdx.x + 256 * e;
-      if (p < D) ga[p] = 0.f;
+  auto store = [&](int64_t c, float4 v) __attribute__((always_inline)) {
+    if (VEC_OUT && c + 3 < D) {
+      *(float4*)(ga + c) = v;
+    } else {
+      if (c < D) ga[c] = v.x;
+      if (c + 1 < D) ga[c + 1] = v.y;
+      if (c + 2 < D) ga[c + 2] = v.z;
+      if (c + 3 < D) ga[c + 3] = v.w;
     }
+  };
+  if (!touch[a]) {
+#pragma unroll
+    for (int v = 0; v < GB_VEC; ++v) store(cbase + 1024 * v, make_float4(0.f, 0.f, 0.f, 0.f));
     return;
   }
+  // FP32 source vector of row r at the thread's columns (zero past D)
+  auto load = [&](int64_t r, int v) __attribute__((always_inline)) {
+    const int64_t c = cbase + 1024 * v;
+    const float* p = X + r * ldx + c;
+    if (c + 3 < D) return *(const float4*)p;
+    return make_float4(c < D ? p[0] : 0.f, c + 1 < D ? p[1] : 0.f, c + 2 < D ? p[2] : 0.f,
+                       c + 3 < D ? p[3] : 0.f);
+  };
+  double acc[GB_VEC][4];
+  double xa[GB_VEC][4];
+#pragma unroll
+  for (int v = 0; v < GB_VEC; ++v) {
+    const float4 x = load(a, v);
+    xa[v][0] = x.x, xa[v][1] = x.y, xa[v][2] = x.z, xa[v][3] = x.w;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) acc[v][e] = 0.0;
+  }
   const double invk = 1.0 / (double)k;
-  const float* xa = X + (int64_t)a * ldx;
-  {
-    double acc[GCOLS];
-    double xav[GCOLS];
+  auto term = [&](int64_t b, double c) __attribute__((always_inline)) {
+    float4 xb[GB_VEC];
 #pragma unroll
-    for (int e = 0; e < GCOLS; ++e) {
-      const int64_t p = c0 + threadIdx.x + 256 * e;
-      acc[e] = 0.0;
-      xav[e] = p < D ? (double)xa[p] : 0.0;
-    }
-    // W_ab: a = t + m, b = j + m for j in N_t
-    for (int m = 0; m < L; ++m) {
-      const int t = a - m;
-      if (t < 0 || t >= np) continue;
-      const double wt = w[t];
-      if (wt == 0.0) continue;
-      const double c = wt * invk;
-      for (int q = 0; q < k; ++q) {
-        const int j = idx[(int64_t)t * k + q];
-        if (j < 0 || j >= np) continue;
-        const float* xb = X + (int64_t)(j + m) * ldx;
+    for (int v = 0; v < GB_VEC; ++v) xb[v] = load(b, v);
 #pragma unroll
-        for (int e = 0; e < GCOLS; ++e) {
-          const int64_t p = c0 + threadIdx.x + 256 * e;
-          if (p < D) acc[e] += c * (xav[e] - (double)xb[p]);
-        }
-      }
+    for (int v = 0; v < GB_VEC; ++v) {
+      acc[v][0] += c * (xa[v][0] - (double)xb[v].x);
+      acc[v][1] += c * (xa[v][1] - (double)xb[v].y);
+      acc[v][2] += c * (xa[v][2] - (double)xb[v].z);
+      acc[v][3] += c * (xa[v][3] - (double)xb[v].w);
     }
-    // W_ba: a = j + m with j in N_t, b = t + m
-    for (int m = 0; m < L; ++m) {
-      const int j = a - m;
+  };
+  // W_ab: a = t + m, b = j + m for j in N_t
+  for (int m = 0; m < L; ++m) {
+    const int t = a - m;
+    if (t < 0 || t >= np) continue;
+    const double wt = w[t];
+    if (wt == 0.0) continue;
+    const double c = wt * invk;
+    for (int q = 0; q < k; ++q) {
+      const int j = idx[(int64_t)t * k + q];
       if (j < 0 || j >= np) continue;
-      for (int r = ptr[j]; r < ptr[j + 1]; ++r) {
-        const int t = rev[r];
-        const double c = w[t] * invk;
-        const float* xb = X + (int64_t)(t + m) * ldx;
-#pragma unroll
-        for (int e = 0; e < GCOLS; ++e) {
-          const int64_t p = c0 + threadIdx.x + 256 * e;
-          if (p < D) acc[e] += c * (xav[e] - (double)xb[p]);
-        }
-      }
-    }
-#pragma unroll
-    for (int e = 0; e < GCOLS; ++e) {
-      const int64_t p = c0 + threadIdx.x + 256 * e;
-      if (p < D) ga[p] = (float)(2.0 * acc[e]);
+      term(j + m, c);
     }
   }
+  // W_ba: a = j + m with j in N_t, b = t + m
+  for (int m = 0; m < L; ++m) {
+    const int j = a - m;
+    if (j < 0 || j >= np) continue;
+    for (int r = ptr[j]; r < ptr[j + 1]; ++r) {
+      const int t = rev[r];
+      term(t + m, w[t] * invk);
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < GB_VEC; ++v)
+    store(cbase + 1024 * v, make_float4((float)(2.0 * acc[v][0]), (float)(2.0 * acc[v][1]),
+                                        (float)(2.0 * acc[v][2]), (float)(2.0 * acc[v][3])));
 }
 
 }  // namespace
 
 hipError_t launch_backward(const float* X, int64_t ldx, int64_t T, int64_t D,
                            int L, int k, const int32_t* idx, const double* w,
-                           float* g, int64_t ldg, int32_t* cnt, int32_t* ptr,
-                           int32_t* fill, int32_t* rev, hipStream_t s) {
+                           float* g, int64_t ldg, int32_t* zeroed, int32_t* ptr,
+                           int32_t* rev, hipStream_t s) {
+  // zeroed: the contiguous int32 arrays cnt [np], fill [np], touch [T]
   const int np = (int)(T - L + 1);
+  int32_t* cnt = zeroed;
+  int32_t* fill = zeroed + np;
+  int32_t* touch = zeroed + 2 * (int64_t)np;
+  const int64_t nz = 2 * (int64_t)np + T;
   const int64_t nk = (int64_t)np * k;
   const unsigned gb = (unsigned)((np + 255) / 256);
   const unsigned gk = (unsigned)((nk + 255) / 256);
-  hipLaunchKernelGGL(fill_i32_kernel, dim3(gb), dim3(256), 0, s, cnt, (int64_t)np, 0);
-  hipLaunchKernelGGL(fill_i32_kernel, dim3(gb), dim3(256), 0, s, fill, (int64_t)np, 0);
-  hipLaunchKernelGGL(rev_count_kernel, dim3(gk), dim3(256), 0, s, idx, w, np, k, cnt);
+  hipError_t e;
+  hipLaunchKernelGGL(fill_i32_kernel, dim3((unsigned)((nz + 255) / 256)), dim3(256), 0, s,
+                     zeroed, nz, 0);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(rev_count_kernel, dim3(gk), dim3(256), 0, s, idx, w, np, k, L, cnt, touch);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, cnt, np, ptr);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(rev_fill_kernel, dim3(gk), dim3(256), 0, s, idx, w, np, k, ptr,
                      fill, rev);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(rev_sort_kernel, dim3(gb), dim3(256), 0, s, ptr, np, rev);
-  const unsigned col_blocks = (unsigned)((D + 256 * GCOLS - 1) / (256 * GCOLS));
-  hipLaunchKernelGGL(grad_rows_kernel, dim3((unsigned)T, col_blocks), dim3(256), 0, s, X, ldx,
-                     (int)T, D, L, k, idx, w, ptr, rev, g, ldg);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const dim3 grid((unsigned)T, (unsigned)((D + GB_COLS - 1) / GB_COLS));
+  const bool vec_out = ldg % 4 == 0 && ((uintptr_t)g % 16) == 0;
+  if (vec_out)
+    hipLaunchKernelGGL(grad_rows_kernel<true>, grid, dim3(256), 0, s, X, ldx, (int)T, D, L, k,
+                       idx, w, ptr, rev, touch, g, ldg);
+  else
+    hipLaunchKernelGGL(grad_rows_kernel<false>, grid, dim3(256), 0, s, X, ldx, (int)T, D, L, k,
+                       idx, w, ptr, rev, touch, g, ldg);
   return hipGetLastError();
 }
 

@@ -35,6 +35,8 @@
 // that the later fields' rows of the band's columns are contiguous too.
 #include <type_traits>
 
+#include "dist_clamp.h"
+#include "fused_walk.h"
 #include "internal.h"
 
 namespace traknn {
@@ -222,16 +224,41 @@ __device__ __forceinline__ void interleave_reads() {
   }
 }
 
-template <int PREC, bool BAND>
+// Fused mode (FUSE 1: establishing launch, 2: filtering launch): the tile's
+// trajectory stride is fg.B = 256 - (L - 1) rounded down to a multiple of 4,
+// so consecutive tiles overlap by L - 1 fields and hold every term of Eq. 2
+// of their trajectory pairs. After the main loop nothing is stored: the
+// distances are staged in LDS in four parts -- the rows of the first and
+// second half of the tile's trajectory rows, then (transposed) the columns of
+// either half of its trajectory columns, each with its L - 1 halo -- and the
+// tile walk (fused_walk.h) of each part offers every pair to its row (row
+// parts) or to its column (column parts). The distances are formed exactly as
+// the matrix mode forms them (same operands, same order, the smaller field on
+// the A side), so the two modes agree bit for bit wherever the FP64 window
+// sums are exact.
+constexpr int FPITCH = TILE + 1;  // floats per staged row (odd: transposed reads)
+constexpr int FUSED_MAX_STAGED = (GRAM_TILE - 16) / 2 + 15;  // rows of a part, L <= 16
+constexpr int FUSED_VAL_BYTES = FUSED_MAX_STAGED * FPITCH * 4;
+constexpr int GRAM_LDS = GRAM_STAGES * 2 * OPER_BYTES + NORM_LDS;
+constexpr int FUSED_LDS = FUSED_VAL_BYTES + 128 * 8 > GRAM_LDS ? FUSED_VAL_BYTES + 128 * 8 : GRAM_LDS;
+
+template <int PREC, bool BAND, int FUSE = 0>
 __global__ __launch_bounds__(GRAM_THREADS, 1) void gram_kernel(
     const char* __restrict__ xc, int64_t pitch, int nstages,
     const float* __restrict__ ncs, int64_t T, int64_t Tpad, int nb, int64_t ntiles,
     int64_t a_row0, int nbi, int64_t rows_out, int J0, float* __restrict__ S, int64_t ldS,
-    float* __restrict__ ST, int64_t ldST) {
-  __shared__ __attribute__((aligned(16))) char lds[GRAM_STAGES * 2 * OPER_BYTES + NORM_LDS];
+    float* __restrict__ ST, int64_t ldST, FusedGeom fg, const double* __restrict__ fbound,
+    FusedOut fout) {
+  __shared__ __attribute__((aligned(16))) char lds[FUSE ? FUSED_LDS : GRAM_LDS];
   float* const nrm = (float*)(lds + GRAM_STAGES * 2 * OPER_BYTES);  // [2][I 256 | J 256]
   int I, J;
-  if constexpr (BAND) {
+  if constexpr (FUSE == 1) {
+    if (!fused_establish_tile(blockIdx.x, fg, I, J)) return;
+  } else if constexpr (FUSE == 2) {
+    if (!decode_tile(blockIdx.x, fg.nbt, fg.nbt, ntiles, I, J)) return;
+    for (int q = 0; q < fg.nh; ++q)
+      if (J - I == fg.h[q]) return;  // done by the establishing launch
+  } else if constexpr (BAND) {
     // the band's tiles that hold entries above the diagonal: J >= J0 + I,
     // the upper triangle of the columns from J0 on, cut to the band's rows
     if (!decode_tile(blockIdx.x, nb - J0, nbi, ntiles, I, J)) return;
@@ -240,8 +267,8 @@ __global__ __launch_bounds__(GRAM_THREADS, 1) void gram_kernel(
     if (!decode_tile(blockIdx.x, nb, nb, ntiles, I, J)) return;
   }
   // first fields of the tile's A and B panels
-  const int64_t arow = (BAND ? a_row0 : 0) + (int64_t)I * TILE;
-  const int64_t brow = (int64_t)J * TILE;
+  const int64_t arow = FUSE ? (int64_t)I * fg.B : (BAND ? a_row0 : 0) + (int64_t)I * TILE;
+  const int64_t brow = FUSE ? (int64_t)J * fg.B : (int64_t)J * TILE;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -376,6 +403,51 @@ __global__ __launch_bounds__(GRAM_THREADS, 1) void gram_kernel(
   }
   __syncthreads();  // every wave is done with the operand buffers
 
+  if constexpr (FUSE != 0) {
+    float* V = (float*)lds;                            // [staged][FPITCH]
+    double* rbl = (double*)(lds + FUSED_VAL_BYTES);    // recipient bounds
+    const int hs = fg.B / 2;                           // recipients per part
+    const int Rs = hs + fg.L - 1;                      // staged rows (columns)
+    const int grp = w >> 2, l = (w & 3) * 64 + lane;   // two walks of 4 waves
+#pragma unroll 1
+    for (int part = 0; part < 4; ++part) {
+      const bool cols = part >= 2;
+      const int off = (part & 1) * hs;  // first staged tile row (column)
+#pragma unroll
+      for (int bm = 0; bm < BM; ++bm) {
+        const int rb = wm * WT_M + bm * 32;
+        if (!cols && (rb + 32 <= off || rb >= off + Rs)) continue;
+#pragma unroll
+        for (int bn = 0; bn < BN; ++bn) {
+          const int cb = wn * WT_N + bn * 32;
+          if (cols && (cb + 32 <= off || cb >= off + Rs)) continue;
+          const int col = cb + (lane & 31);
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const int row = rb + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+            const int rel = (cols ? col : row) - off;
+            if (rel >= 0 && rel < Rs)
+              V[rel * FPITCH + (cols ? row : col)] = clamp_distance(-2.f * acc[bm][bn][r]);
+          }
+        }
+      }
+      const int p0 = (cols ? J : I) * fg.B + off, q0 = (cols ? I : J) * fg.B;
+      if constexpr (FUSE == 2) {
+        for (int p = tid; p < hs; p += GRAM_THREADS)
+          rbl[p] = p0 + p < fg.np ? fbound[p0 + p] : -1.0;
+      }
+      __syncthreads();
+      if constexpr (FUSE == 1)
+        tile_establish(V, FPITCH, 1, fg.B, 0, hs, p0, q0, cols ? -1 : 1, fg.L, fg.np, fg.k, w,
+                       GRAM_THREADS / 64, lane, fout);
+      else
+        tile_walk(V, FPITCH, 1, fg.B, grp * (hs / 2), (grp + 1) * (hs / 2), p0, q0,
+                  cols ? -1 : 1, fg.L, fg.np, fg.k, rbl, l, lane, fout);
+      __syncthreads();
+    }
+    return;
+  }
+
   // Epilogue through LDS (the operand buffers are free now): d = -2 acc.
   // Accumulator r of
   // lane l in a 32x32 block holds row 8*(r/4) + 4*(l/32) + r%4, column l%32;
@@ -419,7 +491,7 @@ __global__ __launch_bounds__(GRAM_THREADS, 1) void gram_kernel(
             const float v = -2.f * src[r];
             // band mode: a field's distance to itself is stored as 0, as the
             // mirrored pass stores it in the symmetric mode
-            S[i * ldS + (j - c0)] = (BAND && a_row0 + i == j) ? 0.f : (v > 0.f ? v : 0.f);
+            S[i * ldS + (j - c0)] = (BAND && a_row0 + i == j) ? 0.f : clamp_distance(v);
           }
         }
       }
@@ -440,8 +512,7 @@ __global__ __launch_bounds__(GRAM_THREADS, 1) void gram_kernel(
         float f[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const float v = -2.f * g[e];
-          f[e] = v > 0.f ? v : 0.f;
+          f[e] = clamp_distance(-2.f * g[e]);
         }
         if constexpr (BAND) {
           // i0 is a band row: field a_row0 + i0
@@ -494,9 +565,12 @@ hipError_t launch_gram_band(const void* xc, const float* ncs, int64_t T, int64_t
   const char* x = (const char*)xc;
   const bool band = a_row0 >= 0;
   if (!band) rows_out = T;
+  const FusedGeom fg{};
+  const FusedOut fo{};
 #define TRAKNN_GRAM_LAUNCH(P, B)                                                          \
   hipLaunchKernelGGL((gram_kernel<P, B>), grid, dim3(GRAM_THREADS), 0, s, x, pitch, nstages, \
-                     ncs, T, Tpad, nb, ntiles, a_row0, nbi, rows_out, J0, S, ldS, ST, ldST)
+                     ncs, T, Tpad, nb, ntiles, a_row0, nbi, rows_out, J0, S, ldS, ST, ldST, \
+                     fg, nullptr, fo)
   switch (precision) {
     case TRAKNN_FP32:
       if (band) TRAKNN_GRAM_LAUNCH(TRAKNN_FP32, true);
@@ -512,6 +586,39 @@ hipError_t launch_gram_band(const void* xc, const float* ncs, int64_t T, int64_t
       break;
   }
 #undef TRAKNN_GRAM_LAUNCH
+  return hipGetLastError();
+}
+
+hipError_t launch_gram_fused(const void* xc, const float* ncs, int64_t T, int64_t Tpad,
+                             int64_t Dpad, int precision, const FusedGeom& g, bool establish,
+                             const double* bound, const FusedOut& out, hipStream_t s) {
+  const int64_t pitch = Dpad * elem_bytes(precision);
+  const int nstages = (int)(Dpad / stage_k(precision));
+  const int64_t ntiles = establish ? fused_establish_tiles(g) : (int64_t)g.nbt * (g.nbt + 1) / 2;
+  if (ntiles <= 0) return hipSuccess;
+  // establishing tiles in their own order; the rest XCD-aware, as the matrix mode
+  const dim3 grid((unsigned)(establish ? ntiles
+                                       : (ntiles + NUM_XCD - 1) / NUM_XCD * NUM_XCD));
+  const char* x = (const char*)xc;
+#define TRAKNN_GRAM_FUSED(P, F)                                                           \
+  hipLaunchKernelGGL((gram_kernel<P, false, F>), grid, dim3(GRAM_THREADS), 0, s, x, pitch, \
+                     nstages, ncs, T, Tpad, 0, ntiles, (int64_t)0, 0, T, 0, nullptr,        \
+                     (int64_t)0, nullptr, (int64_t)0, g, bound, out)
+  switch (precision) {
+    case TRAKNN_FP32:
+      if (establish) TRAKNN_GRAM_FUSED(TRAKNN_FP32, 1);
+      else TRAKNN_GRAM_FUSED(TRAKNN_FP32, 2);
+      break;
+    case TRAKNN_BF16X3:
+      if (establish) TRAKNN_GRAM_FUSED(TRAKNN_BF16X3, 1);
+      else TRAKNN_GRAM_FUSED(TRAKNN_BF16X3, 2);
+      break;
+    default:
+      if (establish) TRAKNN_GRAM_FUSED(TRAKNN_FP16, 1);
+      else TRAKNN_GRAM_FUSED(TRAKNN_FP16, 2);
+      break;
+  }
+#undef TRAKNN_GRAM_FUSED
   return hipGetLastError();
 }
 

@@ -47,10 +47,33 @@ inline int colstat_chunks(int64_t T) {
   return (int)(((T + s - 1) / s + COLSTAT_ROWS - 1) / COLSTAT_ROWS);
 }
 
+// Fused (S-free) mode. Tiles of FUSED_F64_TILE (FP64 vector kernel) or
+// GRAM_TILE (MFMA Gram) snapshot rows and columns pair B = tile - (L - 1)
+// trajectories (rounded down to a multiple of 4 for the MFMA tiles) with B,
+// so consecutive tiles overlap by L - 1 fields; nbt = ceil(n' / B)
+// block-rows. The establishing launch covers the tiles (I, I + h) of the
+// offsets h[0] = 0 < h[1] < ... (the diagonal band and a few far ones, about
+// one round of the GPU); the filtering launch the rest of the upper triangle.
+constexpr int FUSED_F64_TILE = 128;
+constexpr int FUSED_MAX_OFFSETS = 8;
+struct FusedGeom {
+  int T, np, L, k, B, nbt, nh;
+  int h[FUSED_MAX_OFFSETS];
+};
+// Per-row buffers of appended candidates.
+struct FusedOut {
+  int32_t* cnt;  // [n'] entries appended per row (may exceed cap: overflow)
+  double* bd;    // [n'][cap] appended distances
+  int32_t* bi;   // [n'][cap] appended neighbour indices
+  int cap;
+};
+
 struct Layout {
+  // backward first: traknn_score_backward only needs the prefix up to bw_end
+  size_t bw_zero, bw_ptr, bw_rev, bw_end;
   size_t mu_part, mu, ncs, xc, S, ST, part_d, part_i;  // forward
   size_t cpart_d, cpart_i;                             // band mode: column windows
-  size_t bw_cnt, bw_ptr, bw_fill, bw_rev;            // backward
+  size_t f_bound, f_cnt, f_bd, f_bi;                   // fused mode
   size_t total;
 };
 
@@ -70,6 +93,9 @@ struct traknn_plan_s {
   int64_t band_rows; // band mode: rows of S held, rb + L_max - 1 (at most T)
   int64_t ldST;      // band mode: row stride of the transposed band, floats
   int tchunks;       // partial column-sum blocks of the sampled rows
+  int fused;         // fused (S-free) mode
+  traknn::FusedGeom fg;  // fused mode: tile geometry
+  int fcap;          // fused mode: appended candidates held per row
   int win_splits;    // column splits (waves) per window row block (W)
   int col_splits;    // band mode: the same for the column windows
   traknn::Layout lay;
@@ -149,10 +175,31 @@ hipError_t launch_score_prefix(const double* dist, int64_t T, int L_min, int L_m
 hipError_t launch_local_dim(const double* dist, int64_t T, int L_min, int L_max, int k,
                             double* out, hipStream_t s);
 // backward.hip
+// zeroed: 2 (T - L + 1) + T int32 scratch the launch clears itself; ptr:
+// T - L + 2 int32; rev: (T - L + 1) k int32.
 hipError_t launch_backward(const float* X, int64_t ldx, int64_t T, int64_t D,
                            int L, int k, const int32_t* idx, const double* w,
-                           float* g, int64_t ldg, int32_t* cnt, int32_t* ptr,
-                           int32_t* fill, int32_t* rev, hipStream_t s);
+                           float* g, int64_t ldg, int32_t* zeroed, int32_t* ptr,
+                           int32_t* rev, hipStream_t s);
+
+// Fused mode with the MFMA Gram: the establishing (establish = true) or the
+// filtering launch over 256-field tiles of stride g.B.
+hipError_t launch_gram_fused(const void* xc, const float* ncs, int64_t T, int64_t Tpad,
+                             int64_t Dpad, int precision, const FusedGeom& g, bool establish,
+                             const double* bound, const FusedOut& out, hipStream_t s);
+// fused.hip
+int64_t fused_establish_tiles(const FusedGeom& g);
+hipError_t launch_fused_clear(const FusedGeom& g, const FusedOut& out, hipStream_t s);
+hipError_t launch_fused_f64(const float* X, int64_t ldx, int D, const double* mu,
+                            const FusedGeom& g, bool establish, const double* bound,
+                            const FusedOut& out, hipStream_t s);
+hipError_t launch_fused_bound(const FusedGeom& g, const FusedOut& out, double* bound,
+                              hipStream_t s);
+// Final lists from the appended candidates, then the exact recomputation of
+// the rows whose buffers overflowed.
+hipError_t launch_fused_select(const float* X, int64_t ldx, int D, const double* mu,
+                               const FusedGeom& g, const FusedOut& out, int32_t* idx,
+                               double* dist, hipStream_t s);
 
 // Window stage sizing shared by the planner and the launcher: LDS bytes of a
 // workgroup of W waves for a pass of G lengths whose longest is L, k neighbours.

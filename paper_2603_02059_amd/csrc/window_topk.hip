@@ -38,20 +38,10 @@
 #include <utility>
 
 #include "internal.h"
+#include "topk_wave.h"
 
 namespace traknn {
 namespace {
-
-__device__ __forceinline__ double readlane_d(double v, int l) {
-  int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
-  int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
-  return __hiloint2double(hi, lo);
-}
-// (ad, ai) < (bd, bi) lexicographically; bitwise, so it compiles to three
-// compares and two mask operations instead of short-circuit branches.
-__device__ __forceinline__ bool key_less(double ad, int ai, double bd, int bi) {
-  return (ad < bd) | ((ad == bd) & (ai < bi));
-}
 
 // ---------------------------------------------------------------------------
 // Window + top-k kernel for one trajectory length L.
@@ -70,87 +60,6 @@ constexpr int W1_GROUP = 8;   // steps unrolled per group
 static_assert(W1_ROWS % W1_GROUP == 0 && (W1_ROWS & (W1_ROWS - 1)) == 0 && W1_ROWS <= 64,
               "rows per block: a power of two, a multiple of the group, at most a wave");
 #define W1_VALS_BYTES(M) (((size_t)(M) * 64 * sizeof(float) + 15) / 16 * 16)
-
-__device__ __forceinline__ double dpp_shr1_d(double v, double old) {
-  const int lo = __builtin_amdgcn_update_dpp(__double2loint(old), __double2loint(v), 0x138, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(__double2hiint(old), __double2hiint(v), 0x138, 0xF, 0xF, false);
-  return __hiloint2double(hi, lo);
-}
-__device__ __forceinline__ int dpp_shr1_i(int v, int old) {
-  return __builtin_amdgcn_update_dpp(old, v, 0x138, 0xF, 0xF, false);
-}
-
-// Insert the ballot's candidates (D, col) of row s into its sorted list
-// (lane q < k holds entry q while inserting) and refresh the row threshold
-// kept by lane s.
-__device__ __forceinline__ void insert_seq(uint64_t mask, double D, int col, int k,
-                                           double* rd, int* ri, int lane, int s,
-                                           double& thr_d, int& thr_i) {
-  double ed = lane < k ? rd[lane] : __builtin_huge_val();
-  int ei = lane < k ? ri[lane] : INT_MAX;
-  while (mask) {
-    const int src = __builtin_ctzll(mask);
-    mask &= mask - 1;
-    const double cd = readlane_d(D, src);
-    const int ci = __builtin_amdgcn_readlane(col, src);
-    const double kd = readlane_d(ed, k - 1);
-    const int ki = __builtin_amdgcn_readlane(ei, k - 1);
-    if (!key_less(cd, ci, kd, ki)) continue;
-    const double pd = dpp_shr1_d(ed, -__builtin_huge_val());  // lane 0: -inf
-    const int pi = dpp_shr1_i(ei, INT_MIN);
-    const bool lt_prev = key_less(cd, ci, pd, pi);
-    const bool lt_self = key_less(cd, ci, ed, ei);
-    ed = lt_prev ? pd : (lt_self ? cd : ed);
-    ei = lt_prev ? pi : (lt_self ? ci : ei);
-  }
-  if (lane < k) {
-    rd[lane] = ed;
-    ri[lane] = ei;
-  }
-  const double nd = readlane_d(ed, k - 1);
-  const int ni = __builtin_amdgcn_readlane(ei, k - 1);
-  if (lane == s) {
-    thr_d = nd;
-    thr_i = ni;
-  }
-}
-
-// Seed row s's list with the k smallest of this step's 64 candidates: bitonic
-// sort of (D, col) across the wave (invalid lanes carry +inf and a distinct
-// index above every column), lanes q < k keep the q-th smallest.
-__device__ __forceinline__ void seed_row(double d, int c, bool valid, int k, double* rd,
-                                         int* ri, int lane, int s, double& thr_d,
-                                         int& thr_i) {
-  if (!valid) {
-    d = __builtin_huge_val();
-    c = INT_MAX - 64 + lane;
-  }
-#pragma unroll 1
-  for (int size = 2; size <= 64; size <<= 1)
-#pragma unroll 1
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      const double pd = __shfl_xor(d, stride, 64);
-      const int pc = __shfl_xor(c, stride, 64);
-      const bool asc = (lane & size) == 0;
-      const bool lower = (lane & stride) == 0;
-      const bool p_less = key_less(pd, pc, d, c);
-      if ((lower == asc) == p_less) {
-        d = pd;
-        c = pc;
-      }
-    }
-  const bool sentinel = d == __builtin_huge_val();
-  if (lane < k) {
-    rd[lane] = d;
-    ri[lane] = sentinel ? INT_MAX : c;
-  }
-  const double nd = readlane_d(d, k - 1);
-  const int nc = __builtin_amdgcn_readlane(c, k - 1);
-  if (lane == s) {
-    thr_d = nd;
-    thr_i = nd == __builtin_huge_val() ? INT_MAX : nc;
-  }
-}
 
 // One workgroup per row block: wave w scans the w-th of W contiguous ranges
 // of 64-diagonal chunks and keeps its own partial lists. The waves also share

@@ -29,13 +29,19 @@ TRAKNN_ERR_HIP = -4
 TRAKNN_FP32 = 0
 TRAKNN_BF16X3 = 1
 TRAKNN_FP16 = 2
-PRECISIONS = {"fp32": TRAKNN_FP32, "bf16x3": TRAKNN_BF16X3, "fp16": TRAKNN_FP16}
+TRAKNN_FP64 = 3
+PRECISIONS = {"fp32": TRAKNN_FP32, "bf16x3": TRAKNN_BF16X3, "fp16": TRAKNN_FP16,
+              "fp64": TRAKNN_FP64}
+TRAKNN_MODE_MATRIX = 0
+TRAKNN_MODE_FUSED = 1
+MODES = {"matrix": TRAKNN_MODE_MATRIX, "fused": TRAKNN_MODE_FUSED}
 MAX_L = 16
 MAX_K = 64
 STAGES = ("centre_stats", "centre_convert", "gram", "window_topk", "merge")
 
 EXPORTS = ("traknn_plan", "traknn_plan_destroy", "traknn_knn", "traknn_score",
-           "traknn_score_prefix", "traknn_local_dim", "traknn_score_backward", "traknn_status_string", "traknn_set_timing",
+           "traknn_score_prefix", "traknn_local_dim", "traknn_score_backward",
+           "traknn_backward_workspace", "traknn_status_string", "traknn_set_timing",
            "traknn_stage_times")
 
 
@@ -49,7 +55,8 @@ class traknn_config(ctypes.Structure):
     _fields_ = [("T", ctypes.c_int64), ("D", ctypes.c_int64),
                 ("L_min", ctypes.c_int32), ("L_max", ctypes.c_int32),
                 ("k", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("row_batch", ctypes.c_int64)]
+                ("row_batch", ctypes.c_int64), ("mode", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 def _load() -> ctypes.CDLL:
@@ -68,6 +75,7 @@ def _load() -> ctypes.CDLL:
     lib.traknn_score_prefix.argtypes = [vp, vp, vp, vp]
     lib.traknn_local_dim.argtypes = [vp, vp, vp, vp]
     lib.traknn_score_backward.argtypes = [vp, vp, i64, vp, vp, vp, i64, vp, sz, vp]
+    lib.traknn_backward_workspace.argtypes = [vp, ctypes.POINTER(sz)]
     lib.traknn_status_string.argtypes = [i32]
     lib.traknn_status_string.restype = ctypes.c_char_p
     lib.traknn_set_timing.argtypes = [vp, i32]
@@ -105,12 +113,15 @@ def _stream(stream) -> int:
 # One-to-one wrappers of the C entry points
 # --------------------------------------------------------------------------
 def traknn_plan(T: int, D: int, L_min: int, L_max: int, k: int,
-                precision: int | str = TRAKNN_BF16X3, row_batch: int = 0):
+                precision: int | str = TRAKNN_BF16X3, row_batch: int = 0,
+                mode: int | str = TRAKNN_MODE_MATRIX):
     """-> (plan handle, workspace bytes). Pure host call; raises TraknnError."""
     if isinstance(precision, str):
         precision = PRECISIONS[precision]
+    if isinstance(mode, str):
+        mode = MODES[mode]
     cfg = traknn_config(int(T), int(D), int(L_min), int(L_max), int(k),
-                        int(precision), int(row_batch))
+                        int(precision), int(row_batch), int(mode), 0)
     h = ctypes.c_void_p()
     ws = ctypes.c_size_t()
     _ck(_lib.traknn_plan(ctypes.byref(cfg), ctypes.byref(h), ctypes.byref(ws)),
@@ -123,9 +134,10 @@ def traknn_plan_destroy(plan) -> None:
 
 
 def workspace_bytes(T: int, D: int, L_min: int, L_max: int, k: int,
-                    precision: int | str = TRAKNN_BF16X3, row_batch: int = 0) -> int:
+                    precision: int | str = TRAKNN_BF16X3, row_batch: int = 0,
+                    mode: int | str = TRAKNN_MODE_MATRIX) -> int:
     """Workspace of a plan, from the planner alone (no GPU involved)."""
-    h, ws = traknn_plan(T, D, L_min, L_max, k, precision, row_batch)
+    h, ws = traknn_plan(T, D, L_min, L_max, k, precision, row_batch, mode)
     traknn_plan_destroy(h)
     return ws
 
@@ -180,6 +192,13 @@ def traknn_score_backward(plan, X, ldx: int, nbr_idx, grad_scores, grad_X,
         "traknn_score_backward")
 
 
+def traknn_backward_workspace(plan) -> int:
+    """Bytes of workspace traknn_score_backward needs (a prefix of the plan's)."""
+    b = ctypes.c_size_t()
+    _ck(_lib.traknn_backward_workspace(plan, ctypes.byref(b)), "traknn_backward_workspace")
+    return b.value
+
+
 def traknn_status_string(code: int) -> str:
     return status_string(code)
 
@@ -219,15 +238,18 @@ class Plan:
 
     def __init__(self, T: int, D: int, L_min: int, L_max: int | None = None,
                  k: int = 10, precision: str | int = "bf16x3", device=None,
-                 row_batch: int = 0):
+                 row_batch: int = 0, mode: str | int = "matrix"):
         """row_batch > 0 (a multiple of 8) streams the distance matrix in bands
-        of row_batch trajectory rows instead of holding all T x T of it."""
+        of row_batch trajectory rows instead of holding all T x T of it;
+        mode="fused" never stores it (single length)."""
         L_max = L_min if L_max is None else L_max
         self.T, self.D, self.L_min, self.L_max, self.k = T, D, L_min, L_max, k
         self.row_batch = row_batch
         self.precision = PRECISIONS[precision] if isinstance(precision, str) else precision
+        self.mode = MODES[mode] if isinstance(mode, str) else mode
         self.handle, self.ws_bytes = traknn_plan(T, D, L_min, L_max, k, self.precision,
-                                                 row_batch)
+                                                 row_batch, self.mode)
+        self.bw_bytes = traknn_backward_workspace(self.handle)
         self.device = torch.device(device if device is not None else "cuda")
         self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
         self.NL = L_max - L_min + 1
@@ -282,6 +304,11 @@ class Plan:
         traknn_local_dim(self.handle, dist, out, stream)
         return out
 
+    def release_workspace(self):
+        """Free the forward workspace; backward then allocates only the small
+        prefix it needs."""
+        self.ws = None
+
     def backward(self, X: torch.Tensor, idx: torch.Tensor, grad_scores: torch.Tensor,
                  grad_X=None, stream=None):
         X = _as_fields(X)
@@ -289,8 +316,13 @@ class Plan:
             grad_X = torch.empty((self.T, self.D), dtype=torch.float32, device=self.device)
         gs = grad_scores.reshape(-1).to(torch.float64).contiguous()
         idx = idx.reshape(-1, self.k).contiguous()
+        if self.ws is not None:
+            ws, nbytes = self.ws, self.ws_bytes
+        else:
+            ws = torch.empty(self.bw_bytes, dtype=torch.uint8, device=self.device)
+            nbytes = self.bw_bytes
         traknn_score_backward(self.handle, X, X.stride(0), idx, gs, grad_X,
-                              grad_X.stride(0), self.ws, self.ws_bytes, stream)
+                              grad_X.stride(0), ws, nbytes, stream)
         return grad_X
 
     def set_timing(self, enable: bool = True):
@@ -301,11 +333,11 @@ class Plan:
 
 
 def knn(X: torch.Tensor, L: int, k: int, precision: str = "bf16x3",
-        L_max: int | None = None, row_batch: int = 0):
+        L_max: int | None = None, row_batch: int = 0, mode: str = "matrix"):
     """Neighbour lists (idx [NL, n', k] int32, dist [NL, n', k] float64)."""
     X = _as_fields(X)
     p = Plan(X.shape[0], X.shape[1], L, L_max, k, precision, device=X.device,
-             row_batch=row_batch)
+             row_batch=row_batch, mode=mode)
     try:
         return p.knn(X)
     finally:
@@ -314,7 +346,13 @@ def knn(X: torch.Tensor, L: int, k: int, precision: str = "bf16x3",
 
 class TraknnScore(torch.autograd.Function):
     """s = rarity scores (Eq. 3) of every length-L trajectory of X; backward
-    gives dF/dX with the neighbour sets held fixed."""
+    gives dF/dX with the neighbour sets held fixed.
+
+    Between forward and backward only the plan handle, X and the neighbour
+    lists are kept: the forward workspace (the distance matrix) is freed as
+    soon as the scores exist, and backward allocates just the reverse-list
+    scratch it needs. The plan is released with the graph, so a backward
+    with retain_graph=True can run again."""
 
     @staticmethod
     def forward(ctx, X: torch.Tensor, L: int, k: int, precision: str = "bf16x3"):
@@ -322,18 +360,18 @@ class TraknnScore(torch.autograd.Function):
         p = Plan(Xf.shape[0], Xf.shape[1], L, L, k, precision, device=Xf.device)
         idx, dist = p.knn(Xf)
         s = p.score(dist)[0]
+        p.release_workspace()
+        idx0 = idx[0]
         ctx.plan = p
         ctx.shape = X.shape
-        ctx.save_for_backward(Xf, idx)
-        ctx.mark_non_differentiable(idx)
-        return s, idx[0]
+        ctx.save_for_backward(Xf, idx0)
+        ctx.mark_non_differentiable(idx0)
+        return s, idx0
 
     @staticmethod
     def backward(ctx, grad_s, grad_idx):
-        Xf, idx = ctx.saved_tensors
-        p = ctx.plan
-        g = p.backward(Xf, idx[0], grad_s.to(torch.float64))
-        p.close()
+        Xf, idx0 = ctx.saved_tensors
+        g = ctx.plan.backward(Xf, idx0, grad_s.to(torch.float64))
         return g.reshape(ctx.shape), None, None, None
 
 

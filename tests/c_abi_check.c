@@ -53,6 +53,19 @@ int main(void) {
   c.L_min = 5;
   c.precision = 7;
   CHECK(traknn_plan(&c, &p, &ws) == TRAKNN_ERR_INVALID_ARG);
+  /* FP64 only in fused mode; the fused mode holds no distance matrix */
+  c.L_max = 5;
+  c.precision = TRAKNN_FP64;
+  CHECK(traknn_plan(&c, &p, &ws) == TRAKNN_ERR_UNSUPPORTED);
+  c.mode = TRAKNN_MODE_FUSED;
+  size_t ws_fused = 0;
+  CHECK(traknn_plan(&c, &p, &ws_fused) == TRAKNN_OK);
+  CHECK(ws_fused < (size_t)27394 * 27456 * 4 / 4);
+  CHECK(traknn_plan_destroy(p) == TRAKNN_OK);
+  c.mode = 5;
+  CHECK(traknn_plan(&c, &p, &ws) == TRAKNN_ERR_INVALID_ARG);
+  c.mode = TRAKNN_MODE_MATRIX;
+  c.precision = TRAKNN_BF16X3;
   CHECK(traknn_plan(NULL, &p, &ws) == TRAKNN_ERR_INVALID_ARG);
 
   /* calls on a NULL plan enqueue nothing */

@@ -12,12 +12,13 @@ Neighbour sets are unique except at (near-)ties, so the rule is:
     ``tol`` of delta_k;
   * scores match within ``tol`` (relative; absolute 0 where the oracle's is 0).
 
-For the SLP-shaped workloads these are exactly the stated tolerances
-(``norm_tol = 0``). Off-workload edge cases (L = 1, k = 1, odd grids) can hold
-pairs whose distance is a small fraction of their norms; there the Gram
-identity (Eq. 4) evaluated with FP32 accumulation has an error proportional to
-the norms, not the distance, so those tests add ``norm_tol`` times the pair's
-sum of centred snapshot norms to every allowance (see ``gram_norm_tol``).
+The set and score rules are always exactly these. Off-workload edge cases
+(L = 1, k = 1, odd grids) can hold pairs whose distance is a small fraction of
+their norms; there the Gram identity (Eq. 4) evaluated with FP32 accumulation
+has an error proportional to the norms, not the distance, so those tests add
+``norm_tol`` times the pair's sum of centred snapshot norms to the allowance of
+each individual neighbour distance (see ``gram_norm_tol``), and to nothing
+else. Every call logs its error statistics (``_log_stats``).
 """
 from __future__ import annotations
 
@@ -64,10 +65,31 @@ def _pair_normsum(N, L, t, js):
     return sum(N[t + m] + N[js + m] for m in range(L))
 
 
+def _log_stats(stats: dict, label: str | None) -> None:
+    """Append one JSON line of error statistics to gpurun_out/parity_stats.jsonl
+    (the folder a GPU run brings back) under the running test's name."""
+    import json
+    import os
+    name = label or os.environ.get("PYTEST_CURRENT_TEST", "?").split(" ")[0]
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = os.path.join(root, "gpurun_out")
+    try:
+        os.makedirs(out, exist_ok=True)
+        with open(os.path.join(out, "parity_stats.jsonl"), "a") as f:
+            f.write(json.dumps({"test": name, **stats}) + "\n")
+    except OSError:
+        pass
+
+
 def check_rows(X, L: int, k: int, rows, gidx, gdist, gscore, tol: float,
-               ref=None, norm_tol: float = 0.0) -> dict:
+               ref=None, norm_tol: float = 0.0, label: str | None = None) -> dict:
     """Check GPU outputs for ``rows`` (gidx/gdist [len(rows), k], gscore
-    [len(rows)]) against the oracle. Returns error statistics."""
+    [len(rows)]) against the oracle. Returns error statistics, which are also
+    logged before any assertion fires.
+
+    The set rule (differences only where the oracle gap is below ``tol``) and
+    the score rule (relative error at most ``tol``) are always the stated
+    ones. ``norm_tol`` only widens the per-neighbour distance check."""
     rows = np.asarray(rows, dtype=np.int64)
     N = snapshot_norms(X) if norm_tol > 0 else None
     if ref is None:
@@ -78,10 +100,9 @@ def check_rows(X, L: int, k: int, rows, gidx, gdist, gscore, tol: float,
     gidx = np.asarray(gidx)
     gdist = np.asarray(gdist, dtype=np.float64)
     gscore = np.asarray(gscore, dtype=np.float64)
-    max_d_err = 0.0
-    max_s_err = 0.0
-    d_errs, s_errs = [], []
+    d_errs, s_errs, fails = [], [], []
     set_diff_rows = 0
+    min_gap_diff = None
     for r, t in enumerate(rows):
         gi = gidx[r]
         assert np.all((gi >= 0) & (gi < n)), f"row {t}: index out of range {gi}"
@@ -96,36 +117,39 @@ def check_rows(X, L: int, k: int, rows, gidx, gdist, gscore, tol: float,
         aerr = np.abs(gdist[r] - od)
         scale = np.maximum(np.abs(od), 1e-300)
         derr = np.where(od == 0, np.abs(gdist[r]), aerr / scale)
-        max_d_err = max(max_d_err, float(derr.max()))
         d_errs.append(derr)
-        assert np.all(aerr <= allow), (f"row {t}: distance error {derr.max():.3e} "
-                                       f"beyond tolerance (tol {tol}, norm_tol {norm_tol})")
+        if not np.all(aerr <= allow):
+            fails.append(f"row {t}: distance error {derr.max():.3e} beyond tolerance "
+                         f"(tol {tol}, norm_tol {norm_tol})")
         if set(gi.tolist()) != set(ridx[r].tolist()):
             set_diff_rows += 1
             dk = rdist[r, -1]
-            if norm_tol > 0:
-                # near-tie: the (k+1)-th oracle distance lies within two
-                # allowances of the k-th
-                slack = 2 * (tol * dk + norm_tol * _pair_normsum(N, L, t, ridx[r, -1:])[0])
-            else:
-                slack = tol * dk  # the stated rule: gap below tol
-            assert rgap[r] * dk <= slack, (
-                f"row {t}: neighbour set differs with oracle gap {rgap[r]:.3e}: "
-                f"gpu {sorted(gi)} oracle {sorted(ridx[r])}")
+            slack = tol * dk  # the stated rule: the oracle gap is below tol
+            g = float(rgap[r])
+            min_gap_diff = g if min_gap_diff is None else min(min_gap_diff, g)
+            if not rgap[r] * dk <= slack:
+                fails.append(f"row {t}: neighbour set differs with oracle gap {g:.3e}: "
+                             f"gpu {sorted(gi)} oracle {sorted(ridx[r])}")
             extra = [j for j in gi.tolist() if j not in set(ridx[r].tolist())]
             for j in extra:
-                assert abs(drows[r, j] - dk) <= slack, (
-                    f"row {t}: gpu neighbour {j} is not a near-tie of the k-th")
-        sallow = tol * abs(rscore[r]) + (float(np.mean(extra_allow)) if norm_tol > 0 else 0.0)
+                if not abs(drows[r, j] - dk) <= slack:
+                    fails.append(f"row {t}: gpu neighbour {j} is not a near-tie of the k-th")
         if rscore[r] == 0:
             serr = abs(gscore[r])
         else:
             serr = abs(gscore[r] - rscore[r]) / abs(rscore[r])
-        max_s_err = max(max_s_err, float(serr))
         s_errs.append(serr)
-        assert abs(gscore[r] - rscore[r]) <= sallow or serr <= tol, (
-            f"row {t}: score error {serr:.3e} beyond tolerance")
-    return {"max_dist_rel_err": max_d_err, "max_score_rel_err": max_s_err,
-            "p99_dist_rel_err": float(np.percentile(np.concatenate(d_errs), 99)) if d_errs else 0.0,
-            "p99_score_rel_err": float(np.percentile(s_errs, 99)) if s_errs else 0.0,
-            "set_diff_rows": set_diff_rows, "rows": len(rows)}
+        if not serr <= tol:
+            fails.append(f"row {t}: score error {serr:.3e} beyond tolerance {tol}")
+    dcat = np.concatenate(d_errs) if d_errs else np.zeros(1)
+    stats = {"max_dist_rel_err": float(dcat.max()),
+             "max_score_rel_err": float(max(s_errs)) if s_errs else 0.0,
+             "p99_dist_rel_err": float(np.percentile(dcat, 99)),
+             "p99_score_rel_err": float(np.percentile(s_errs, 99)) if s_errs else 0.0,
+             "set_diff_rows": set_diff_rows, "rows": len(rows),
+             "min_oracle_gap_of_differing_rows": min_gap_diff,
+             "tol": tol, "norm_tol": norm_tol, "L": L, "k": k,
+             "failures": len(fails)}
+    _log_stats(stats, label)
+    assert not fails, f"{len(fails)} parity failures; first: " + "; ".join(fails[:3])
+    return stats

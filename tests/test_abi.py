@@ -53,7 +53,11 @@ def _plan_code(**kw):
     (dict(), 0),
     (dict(T=0), -1), (dict(D=0), -1), (dict(L_min=0, L_max=0), -1),
     (dict(L_min=4, L_max=3), -1), (dict(L_min=17, L_max=17), -1),
-    (dict(k=0), -1), (dict(k=65), -1), (dict(precision=3), -1), (dict(precision=-1), -1),
+    (dict(k=0), -1), (dict(k=65), -1), (dict(precision=4), -1), (dict(precision=-1), -1),
+    # FP64 exists in fused mode only; fused mode: one length, no bands
+    (dict(precision=3), -2), (dict(precision=3, mode=1), 0), (dict(mode=1), 0),
+    (dict(mode=2), -1), (dict(mode=1, L_min=1, L_max=3), -2),
+    (dict(mode=1, row_batch=64), -1),
     (dict(L_min=2, L_max=5), -2),
     # band mode: row_batch a non-negative multiple of 8
     (dict(row_batch=128), 0), (dict(row_batch=8), 0), (dict(row_batch=4096), 0),
@@ -213,3 +217,53 @@ def test_row_batch_for_a_memory_budget():
     assert rb >= 16376
     with pytest.raises(ValueError):
         tk.row_batch_for(T, D, L, L, k, max_bytes=1 << 20)
+
+
+def test_distance_clamp_host(tmp_path):
+    """The Gram epilogue's clamp (csrc/dist_clamp.h), compiled for the host:
+    negative rounding residue becomes 0, a NaN or -inf accumulator becomes
+    +inf (never a near neighbour), finite positive values pass unchanged."""
+    src = tmp_path / "clamp.cpp"
+    src.write_text(r'''
+#include <cmath>
+#include <cstdio>
+#include <limits>
+#include "dist_clamp.h"
+int main() {
+  using traknn::clamp_distance;
+  const float inf = std::numeric_limits<float>::infinity();
+  const float nan = std::numeric_limits<float>::quiet_NaN();
+  int bad = 0;
+  bad += clamp_distance(-1e-3f) != 0.f;
+  bad += std::signbit(clamp_distance(-0.f));
+  bad += clamp_distance(0.f) != 0.f;
+  bad += clamp_distance(3.5f) != 3.5f;
+  bad += clamp_distance(1e-30f) != 1e-30f;
+  bad += clamp_distance(inf) != inf;
+  bad += clamp_distance(nan) != inf;
+  bad += clamp_distance(-inf) != inf;
+  std::printf("bad %d\n", bad);
+  return bad;
+}
+''')
+    exe = str(tmp_path / "clamp")
+    subprocess.run(["g++", "-std=c++17", "-O2", "-Wall", "-Werror", "-I",
+                    os.path.join(ROOT, "paper_2603_02059_amd", "csrc"), str(src), "-o", exe],
+                   check=True, capture_output=True, text=True)
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 0, r.stdout + r.stderr
+
+
+def test_backward_workspace_is_a_small_prefix():
+    """The backward's scratch sits at the start of the workspace and is a
+    small fraction of it (the distance matrix is not needed for backward)."""
+    for T, D, L, k, rb in ((27394, 8192, 5, 10, 0), (10957, 8192, 5, 10, 0),
+                           (2000, 64, 3, 7, 512)):
+        h, ws = tk.traknn_plan(T, D, L, L, k, "bf16x3", rb)
+        try:
+            bw = tk.traknn_backward_workspace(h)
+        finally:
+            tk.traknn_plan_destroy(h)
+        n = T - L + 1
+        assert 4 * (3 * n + k * n) <= bw <= ws
+        assert bw < ws / 20

@@ -116,15 +116,28 @@ def test_all_lengths_sweep():
     Lmax = 10
     _say(f"[gpu-full] sweep L=1..{Lmax} T={w.T} D={w.D} k={w.k}")
     idx, dist, s = _run(Xn, 1, Lmax, w.k, "bf16x3")
+    # the same 64 evenly spaced rows (plus both ends, the planted starts and
+    # 8 random rows) for every length, all lengths from one oracle pass
+    n_last = w.T - Lmax + 1
     rng = np.random.default_rng(11)
+    rows = set(np.linspace(0, n_last - 1, 64).astype(int).tolist())
+    rows |= {0, 1, n_last - 1} | {st for st in starts if st < n_last}
+    rows |= set(rng.integers(0, n_last, 8).tolist())
+    rows = np.array(sorted(rows), dtype=np.int64)
+    _say(f"  oracle: {rows.size} rows for each of L=1..{Lmax}")
+    refs = oracle.knn_rows_multi(Xn, Lmax, w.k, rows)
     for L in range(1, Lmax + 1):
         n = w.T - L + 1
         _check_all_rows(idx[L - 1, :n], dist[L - 1, :n], s[L - 1, :n], L, w.k)
         assert np.all(idx[L - 1, n:] == -1) and np.all(np.isnan(s[L - 1, n:]))
-        rows = np.unique(np.concatenate([rng.integers(0, n, 8), [0, n - 1], starts[:2]]))
         stats = check_rows(Xn, L, w.k, rows, idx[L - 1][rows], dist[L - 1][rows],
-                           s[L - 1][rows], precision_tol("bf16x3"))
+                           s[L - 1][rows], precision_tol("bf16x3"), ref=refs[L - 1])
         _say(f"  L={L}: {stats}")
+        # the last rows of each length (only they see the shortest candidate
+        # ranges at the end of the series)
+        tail = np.arange(n - 3, n)
+        check_rows(Xn, L, w.k, tail, idx[L - 1][tail], dist[L - 1][tail], s[L - 1][tail],
+                   precision_tol("bf16x3"))
     # the sweep and single-length runs agree bit for bit (same distance
     # matrix; each length's sums started and slid the same way, whether it
     # shares a pass with another length or not)
@@ -138,9 +151,10 @@ def test_all_lengths_sweep():
 
 @pytest.mark.parametrize("k", [10, 40])
 def test_small_grid_full_length(k):
-    """A small-D shape (4 x 8 grid, D = 32, as after a PCA reduction) at the full
-    length: the Gram is tiny and the window/top-k stage dominates. k = 40 is
-    the largest k of the paper's intrinsic-dimension estimates."""
+    """A small-D shape (4 x 8 grid, D = 32) at the full length: the Gram is tiny
+    and the window/top-k stage dominates. k = 40 is the largest k of the
+    paper's intrinsic-dimension estimates. Scores and sets under the stated
+    rule; the norm-relative allowance widens only the individual distances."""
     T, L = 27394, 5
     _say(f"[gpu-full] small grid T={T} D=32 L={L} k={k}")
     Xn, starts = synth.make_fields(T, 4, 8, sigma=1.0, n_events=20, event_len=5, seed=4)
@@ -150,6 +164,28 @@ def test_small_grid_full_length(k):
     rows = _sample(idx.shape[0], starts, s, 48, L)
     stats = check_rows(Xn, L, k, rows, idx[rows], dist[rows], s[rows],
                        precision_tol("bf16x3"), norm_tol=gram_norm_tol("bf16x3", 32))
+    _say(f"  {stats}")
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "fp32"])
+def test_pca13_full_length(prec):
+    """The paper's 95%-variance PCA shape (Section 5.1: 13 components, d = 5,
+    k = 10): the full workload's fields reduced to their 13 leading principal
+    component scores by a randomized SVD, T = 27394. Stated rule for scores
+    and sets; the norm-relative allowance widens only individual distances."""
+    w = synth.WORKLOADS["full"]
+    if "pca13" not in _DATA:
+        _say("[gpu-full] generating the 13-component PCA reduction of the full workload")
+        _DATA["pca13"] = synth.make_pca_workload(13)
+    Xn, starts, frac = _DATA["pca13"]
+    _say(f"[gpu-full] pca13 T={w.T} D=13 L={w.L} k={w.k} prec={prec} "
+         f"(explained variance {frac:.3f})")
+    idx, dist, s = _run(Xn, w.L, w.L, w.k, prec)
+    idx, dist, s = idx[0], dist[0], s[0]
+    _check_all_rows(idx, dist, s, w.L, w.k)
+    rows = _sample(idx.shape[0], starts, s, 48, w.L)
+    stats = check_rows(Xn, w.L, w.k, rows, idx[rows], dist[rows], s[rows],
+                       precision_tol(prec), norm_tol=gram_norm_tol(prec, 13))
     _say(f"  {stats}")
 
 

@@ -1,0 +1,189 @@
+"""GPU parity of the fused (S-free) mode against the FP64 oracle.
+
+The fused mode never stores the distance matrix: each tile of the upper
+triangle forms its trajectory distances in LDS, offers every pair to both of
+its rows, and only candidates within a row's bound reach HBM; a select
+kernel then takes each row's k nearest. FP64 precision evaluates Eq. 4 in
+FP64 on the vector ALUs, so every check here uses the stated rule with no
+norm-relative allowance at all, including the small-D shapes of the paper's
+PCA comparison. A constant series makes every candidate tie at the bound, so
+the candidate buffers overflow and the exact fallback computes the rows.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2603_02059_amd import synth
+from tests.parity import check_rows
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+TOL = 1e-5
+_DATA = {}
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _run(Xn, L, k, prec="fp64", mode="fused"):
+    from paper_2603_02059_amd import traknn as tk
+    X = torch.from_numpy(np.ascontiguousarray(Xn, dtype=np.float32)).cuda()
+    p = tk.Plan(X.shape[0], X.shape[1], L, L, k, prec, mode=mode)
+    idx, dist = p.knn(X)
+    s = p.score(dist)
+    torch.cuda.synchronize()
+    out = idx.cpu().numpy()[0], dist.cpu().numpy()[0], s.cpu().numpy()[0]
+    p.close()
+    del X
+    torch.cuda.empty_cache()
+    return out
+
+
+def _all_rows(Xn, L, k, got, label):
+    idx, dist, s = got
+    n = Xn.shape[0] - L + 1
+    ref = oracle.knn(Xn, L, k)
+    Dm = oracle.traj_dist(Xn, L)
+    return check_rows(Xn, L, k, np.arange(n), idx, dist, s, TOL,
+                      ref=(ref[0], ref[1], ref[2], ref[3], Dm), label=label)
+
+
+@pytest.mark.parametrize("T,D,L,k", [
+    (512, 1024, 3, 5),     # the tiny workload's shape
+    (300, 5, 2, 9),        # five cells: BF16x3 cannot reach 1e-5 here
+    (613, 77, 6, 3),
+    (700, 1000, 1, 1),     # L = 1, k = 1: snapshot matrix profile
+    (520, 300, 16, 64),    # longest length, largest k
+    (1100, 13, 5, 10),     # several establishing offsets, far tiles
+])
+def test_fused_f64_small(T, D, L, k):
+    _say(f"[gpu-fused] fp64 T={T} D={D} L={L} k={k}")
+    Xn, starts = synth.make_fields(T, 1, D, sigma=2.0, n_events=2, event_len=L, seed=T + D)
+    st = _all_rows(Xn, L, k, _run(Xn, L, k), f"fused fp64 T={T} D={D} L={L} k={k}")
+    _say(f"  {st}")
+
+
+def test_fused_f64_tiny_workload_and_determinism():
+    w = synth.WORKLOADS["tiny"]
+    _say("[gpu-fused] fp64 tiny workload, twice")
+    Xn, starts = synth.make_workload(w)
+    a = _run(Xn, w.L, w.k)
+    b = _run(Xn, w.L, w.k)
+    for u, v in zip(a, b):
+        assert np.array_equal(u, v)
+    _all_rows(Xn, w.L, w.k, a, "fused fp64 tiny")
+    assert int(np.argmax(a[2])) == starts[0]
+
+
+@pytest.mark.parametrize("T,L,k", [(300, 3, 6), (2000, 3, 5)])
+def test_fused_constant_series_ties_and_overflow(T, L, k):
+    """Every distance is 0, so every candidate ties at each row's bound. At
+    T = 2000 each row's ~1990 candidates exceed its buffer of 1024: every row
+    is recomputed by the fallback, and the lists are still the k smallest
+    indices outside the exclusion zone, as the tie rule requires."""
+    _say(f"[gpu-fused] constant series T={T} L={L} k={k}")
+    Xn = np.full((T, 7), 101300.0, dtype=np.float32)
+    idx, dist, s = _run(Xn, L, k)
+    n = T - L + 1
+    for t in range(n):
+        want = [j for j in range(n) if abs(j - t) >= L][:k]
+        assert idx[t].tolist() == want, t
+    assert np.all(dist == 0) and np.all(s == 0)
+
+
+@pytest.mark.parametrize("shape", ["grid32", "pca13"])
+@pytest.mark.parametrize("k", [10, 40])
+def test_fused_f64_small_d_full_length(shape, k):
+    """The PCA-sized shapes at the full length T = 27394 (a 4 x 8 grid, and the
+    full workload reduced to 13 principal components, Section 5.1), L = 5:
+    sampled rows against the oracle under the stated rule with no allowance,
+    every row's list valid."""
+    T, L = 27394, 5
+    if shape not in _DATA:
+        _say(f"[gpu-fused] generating {shape}")
+        if shape == "grid32":
+            _DATA[shape] = synth.make_fields(T, 4, 8, sigma=1.0, n_events=20, event_len=5,
+                                             seed=4)
+        else:
+            Z, starts, _ = synth.make_pca_workload(13)
+            _DATA[shape] = (Z, starts)
+    Xn, starts = _DATA[shape]
+    _say(f"[gpu-fused] fp64 {shape} T={T} D={Xn.shape[1]} L={L} k={k}")
+    idx, dist, s = _run(Xn, L, k)
+    n = T - L + 1
+    t = np.arange(n)[:, None]
+    assert np.all((idx >= 0) & (idx < n)) and np.all(np.abs(idx - t) >= L)
+    d0, d1, i0, i1 = dist[:, :-1], dist[:, 1:], idx[:, :-1], idx[:, 1:]
+    assert np.all((d0 < d1) | ((d0 == d1) & (i0 < i1)))
+    rows = set(np.linspace(0, n - 1, 48).astype(int).tolist()) | {0, 1, n - 2, n - 1}
+    rows |= {st for st in starts if st < n}
+    rows |= set(np.argsort(-s, kind="stable")[:8].tolist())
+    rows = np.array(sorted(rows), dtype=np.int64)
+    st = check_rows(Xn, L, k, rows, idx[rows], dist[rows], s[rows], TOL,
+                    label=f"fused fp64 {shape} k={k}")
+    _say(f"  {st}")
+
+
+@pytest.mark.parametrize("T,D,L,k,prec", [
+    (512, 1024, 3, 5, "bf16x3"),
+    (700, 1000, 4, 7, "fp32"),
+    (613, 77, 6, 3, "fp16"),
+    (520, 300, 16, 64, "bf16x3"),   # longest length: 240-field tile stride
+    (1100, 64, 1, 10, "bf16x3"),    # L = 1: 256-field stride, several offsets
+    (2600, 40, 2, 4, "fp32"),       # ten block-rows, four establishing offsets
+])
+def test_fused_mfma_equals_matrix(T, D, L, k, prec):
+    """The MFMA-fused mode forms each distance from the same operands in the
+    same order as the matrix mode and its window sums are exact, so its lists,
+    distances and scores equal the matrix mode's bit for bit; both are also
+    checked against the oracle on every row."""
+    from tests.parity import gram_norm_tol, precision_tol
+    _say(f"[gpu-fused] mfma {prec} T={T} D={D} L={L} k={k}")
+    Xn, _ = synth.make_fields(T, 1, D, sigma=2.0, n_events=2, event_len=L, seed=T * 3 + D)
+    fused = _run(Xn, L, k, prec, "fused")
+    matrix = _run(Xn, L, k, prec, "matrix")
+    for name, u, v in zip(("indices", "distances", "scores"), fused, matrix):
+        assert np.array_equal(u, v), f"{name} differ from the matrix mode"
+    n = T - L + 1
+    ref = oracle.knn(Xn, L, k)
+    Dm = oracle.traj_dist(Xn, L)
+    st = check_rows(Xn, L, k, np.arange(n), *fused, precision_tol(prec),
+                    ref=(ref[0], ref[1], ref[2], ref[3], Dm),
+                    norm_tol=gram_norm_tol(prec, D), label=f"fused {prec} T={T} D={D}")
+    _say(f"  {st}")
+
+
+@pytest.mark.parametrize("shape,prec", [("full", "bf16x3"), ("grid32", "bf16x3")])
+def test_fused_mfma_full_length_equals_matrix(shape, prec):
+    """At T = 27394: the headline workload (D = 8192) and the 4 x 8 grid, L = 5,
+    k = 10, the fused mode equals the matrix mode bit for bit on every row,
+    and sampled rows match the oracle."""
+    from tests.parity import gram_norm_tol, precision_tol
+    T, L, k = 27394, 5, 10
+    if shape not in _DATA:
+        _say(f"[gpu-fused] generating {shape}")
+        if shape == "grid32":
+            _DATA[shape] = synth.make_fields(T, 4, 8, sigma=1.0, n_events=20, event_len=5,
+                                             seed=4)
+        else:
+            _DATA[shape] = synth.make_workload("full")
+    Xn, starts = _DATA[shape]
+    _say(f"[gpu-fused] mfma {prec} {shape} T={T} D={Xn.shape[1]}")
+    fused = _run(Xn, L, k, prec, "fused")
+    matrix = _run(Xn, L, k, prec, "matrix")
+    for name, u, v in zip(("indices", "distances", "scores"), fused, matrix):
+        assert np.array_equal(u, v), f"{name} differ from the matrix mode"
+    idx, dist, s = fused
+    n = T - L + 1
+    rows = set(np.linspace(0, n - 1, 24).astype(int).tolist()) | {0, n - 1}
+    rows |= {st for st in starts if st < n}
+    rows = np.array(sorted(rows), dtype=np.int64)
+    st = check_rows(Xn, L, k, rows, idx[rows], dist[rows], s[rows], precision_tol(prec),
+                    norm_tol=0.0 if shape == "full" else gram_norm_tol(prec, Xn.shape[1]),
+                    label=f"fused {prec} {shape}")
+    _say(f"  {st}")
+    if shape == "full":
+        del _DATA[shape]

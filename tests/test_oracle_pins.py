@@ -13,6 +13,7 @@ off-by-one exclusion, the wrong tie rule, a transposed operand) fails at least
 one of them.
 """
 import json
+import math
 import os
 
 import numpy as np
@@ -39,10 +40,14 @@ def test_worked_example(golden_dir):
     x = np.array(g["x"], dtype=np.float64)[:, None]
     L = g["L"]
     for case in g["cases"]:
-        idx, dist, score, _ = oracle.knn(x, L, case["k"])
+        idx, dist, score, gap = oracle.knn(x, L, case["k"])
         np.testing.assert_array_equal(idx, np.array(case["idx"]))
         np.testing.assert_array_equal(dist, np.array(case["dist"], dtype=float))
         np.testing.assert_array_equal(score, np.array(case["score"], dtype=float))
+        # the gap decides which set differences the parity rule admits: one
+        # division of exact integers, so bitwise
+        want = [math.inf if q == "inf" else q[0] / q[1] for q in case["gap"]]
+        assert gap.tolist() == want
     gc = g["grad_case"]
     idx, _, _, _ = oracle.knn(x, L, gc["k"])
     grad = oracle.score_grad(x, L, gc["k"], idx, np.array(gc["weights"], float))
@@ -68,8 +73,13 @@ def _py_knn(xs, L, k):
             cands.append((d, j))
         cands.sort()
         best = cands[:k]
+        if len(cands) > k:
+            dk, dk1 = cands[k - 1][0], cands[k][0]
+            gap = (dk1 - dk) / dk if dk > 0 else (math.inf if dk1 > 0 else 0.0)
+        else:
+            gap = math.inf
         out.append(([j for _, j in best], [d for d, _ in best],
-                    sum(d for d, _ in best) / k))
+                    sum(d for d, _ in best) / k, gap))
     return out
 
 
@@ -77,11 +87,12 @@ def _py_knn(xs, L, k):
 def test_pure_python_bruteforce(T, D, L, k):
     X = _int_fields(T, D, seed=T * 7 + L)
     ref = _py_knn(X.tolist(), L, k)
-    idx, dist, score, _ = oracle.knn(X, L, k)
-    for t, (ri, rd, rs) in enumerate(ref):
+    idx, dist, score, gap = oracle.knn(X, L, k)
+    for t, (ri, rd, rs, rg) in enumerate(ref):
         assert idx[t].tolist() == ri
         assert dist[t].tolist() == rd
         assert score[t] == rs
+        assert gap[t] == rg
 
 
 # --------------------------------------------------------------------------
@@ -323,6 +334,42 @@ def test_gradient_translation_invariant():
     g1 = oracle.score_grad(X, L, k, idx, w)
     g2 = oracle.score_grad(X + 777.0, L, k, idx, w)
     assert np.array_equal(g1, g2)
+
+
+def test_gap_is_relative_kth_to_next():
+    """The gap of every row against the sorted full row of the trajectory
+    matrix, recomputed here from the (k)-th and (k+1)-th order statistics: a
+    wrong rank index, a missing exclusion or the wrong denominator fails."""
+    X = synth.random_fields(70, 6, seed=15).astype(np.float64)
+    L, k = 3, 4
+    Dm = cdist(_materialised(X, L), _materialised(X, L), metric="sqeuclidean")
+    n = Dm.shape[0]
+    _, dist, _, gap = oracle.knn(X, L, k)
+    for t in range(n):
+        row = np.sort(Dm[t, np.abs(np.arange(n) - t) >= L])
+        want = (row[k] - row[k - 1]) / row[k - 1]
+        assert gap[t] == pytest.approx(want, rel=1e-9, abs=1e-12)
+        assert dist[t, -1] == pytest.approx(row[k - 1], rel=1e-12)
+
+
+def test_rows_multi_matches_single_length():
+    """One pass over L = 1..L_max gives, bit for bit, the rows of each length's
+    own direct sums (Eq. 2), and +inf past each length's last trajectory."""
+    X = synth.random_fields(60, 7, seed=16, scale=2.0, offset=3.0).astype(np.float64)
+    T, Lmax = X.shape[0], 6
+    rows = np.array([0, 5, 33, T - Lmax], dtype=np.int64)
+    multi = oracle.traj_dist_rows_multi(X, Lmax, rows)
+    for L in range(1, Lmax + 1):
+        n = T - L + 1
+        assert np.array_equal(multi[L - 1, :, :n], oracle.traj_dist_rows(X, L, rows))
+        assert np.all(np.isinf(multi[L - 1, :, n:]))
+    res = oracle.knn_rows_multi(X, Lmax, 3, rows)
+    for L in range(1, Lmax + 1):
+        single = oracle.knn_rows(X, L, 3, rows)
+        for a, b in zip(res[L - 1], single):
+            assert np.array_equal(a, b)
+    with pytest.raises(ValueError):
+        oracle.traj_dist_rows_multi(X, Lmax, np.array([T - Lmax + 1]))
 
 
 def test_rows_mode_matches_full():
