@@ -51,6 +51,7 @@ extern "C" {
 #define TRAKNN_ERR_UNSUPPORTED (-2) /* valid request outside what this library implements */
 #define TRAKNN_ERR_WORKSPACE (-3)   /* workspace pointer NULL/misaligned or too small */
 #define TRAKNN_ERR_HIP (-4)         /* a HIP runtime call or kernel launch failed */
+#define TRAKNN_ERR_SCRATCH_LIMIT (-5) /* plan too large for traknn_knn_noalloc's scratch */
 
 /* Precision of the Gram contraction (Eq. 4). In every mode the fields are first
  * shifted per grid cell by an FP64 mean over at most 2048 evenly strided
@@ -196,6 +197,30 @@ int traknn_plan_destroy(traknn_plan_t plan);
 int traknn_knn(traknn_plan_t plan, const float* X, int64_t ldx, void* workspace,
                size_t workspace_bytes, int32_t* nbr_idx, double* nbr_dist,
                void* stream);
+
+/* Fixed scratch, in bytes, of traknn_knn_noalloc: a plan qualifies when its
+ * workspace_bytes from traknn_plan is at most this (for example T = 2048
+ * fields of D = 1024 cells, whole-matrix mode). */
+#define TRAKNN_NOALLOC_MAX_BYTES (32u << 20)
+
+/* traknn_knn without a caller workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc). The scratch is a fixed TRAKNN_NOALLOC_MAX_BYTES
+ * array in the library's device memory, one per GPU, created with the code
+ * object and held until the process ends; its address is looked up on the
+ * first call on each device. The call allocates and frees nothing. Results
+ * equal traknn_knn's for the same plan and inputs bit for bit (same kernels,
+ * same arithmetic). All calls on one GPU share that GPU's array, so calls
+ * that overlap in time on one GPU (two streams, two threads) race and give
+ * undefined results; calls on one stream are ordered and safe. The kernels
+ * write every scratch byte they read, so nothing needs clearing between
+ * calls.
+ *   plan, X, ldx, nbr_idx, nbr_dist, stream: as for traknn_knn.
+ * Errors: INVALID_ARG; SCRATCH_LIMIT if the plan's workspace_bytes exceed
+ * TRAKNN_NOALLOC_MAX_BYTES (nothing enqueued); HIP (including a failed
+ * scratch lookup); UNSUPPORTED for a device ordinal of 64 or more. */
+int traknn_knn_noalloc(traknn_plan_t plan, const float* X, int64_t ldx, int32_t* nbr_idx,
+                       double* nbr_dist, void* stream);
 
 /* Rarity score (paper, Eq. 3): s_t = (1/k) * sum of the row of nbr_dist, summed
  * in rank order in FP64.

@@ -1,9 +1,11 @@
 // C ABI of the TRAKNN hot path: planning, argument validation, workspace
 // layout and the launch sequence. No C++ exception crosses this boundary and
 // nothing is enqueued unless every argument has been accepted.
+#include <atomic>
 #include <climits>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "internal.h"
@@ -350,6 +352,35 @@ int enqueue_knn(traknn_plan_s* plan, const float* X, int64_t ldx, void* workspac
   return TRAKNN_OK;
 }
 
+// Fixed device scratch of traknn_knn_noalloc, for callers that cannot
+// allocate. Each device that runs the entry point holds one copy until the
+// process ends; its address is looked up once per device with that device
+// current (hipGetSymbolAddress), and only that address is ever used: the
+// array's name in host code does not denote device memory.
+static __device__ __align__(256) char scratch[TRAKNN_NOALLOC_MAX_BYTES];
+
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::atomic<void*> scratch_ptr[SCRATCH_MAX_DEVICES];
+std::mutex scratch_mutex;
+
+int device_scratch(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return TRAKNN_ERR_HIP;
+  if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return TRAKNN_ERR_UNSUPPORTED;
+  void* p = scratch_ptr[dev].load(std::memory_order_acquire);
+  if (!p) {
+    std::lock_guard<std::mutex> lock(scratch_mutex);
+    p = scratch_ptr[dev].load(std::memory_order_relaxed);
+    if (!p) {
+      if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p)
+        return TRAKNN_ERR_HIP;
+      scratch_ptr[dev].store(p, std::memory_order_release);
+    }
+  }
+  *out = p;
+  return TRAKNN_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -366,6 +397,9 @@ const char* traknn_status_string(int status) {
       return "workspace missing, misaligned or too small";
     case TRAKNN_ERR_HIP:
       return "HIP runtime or kernel launch failure";
+    case TRAKNN_ERR_SCRATCH_LIMIT:
+      return "workspace of this plan exceeds the fixed scratch of traknn_knn_noalloc "
+             "(TRAKNN_NOALLOC_MAX_BYTES)";
     default:
       return "unknown status";
   }
@@ -481,6 +515,17 @@ int traknn_knn(traknn_plan_t plan, const float* X, int64_t ldx, void* workspace,
   rc = check_ws(workspace, workspace_bytes, plan->lay.total);
   if (rc) return rc;
   return enqueue_knn(plan, X, ldx, workspace, nbr_idx, nbr_dist, (hipStream_t)stream);
+}
+
+int traknn_knn_noalloc(traknn_plan_t plan, const float* X, int64_t ldx, int32_t* nbr_idx,
+                       double* nbr_dist, void* stream) {
+  if (!plan || !nbr_idx || !nbr_dist) return TRAKNN_ERR_INVALID_ARG;
+  int rc = check_x(plan, X, ldx);
+  if (rc) return rc;
+  if (plan->lay.total > (size_t)TRAKNN_NOALLOC_MAX_BYTES) return TRAKNN_ERR_SCRATCH_LIMIT;
+  void* ws = nullptr;
+  if ((rc = device_scratch(&ws))) return rc;
+  return enqueue_knn(plan, X, ldx, ws, nbr_idx, nbr_dist, (hipStream_t)stream);
 }
 
 int traknn_score(traknn_plan_t plan, const double* nbr_dist, double* scores,

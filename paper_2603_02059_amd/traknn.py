@@ -25,6 +25,8 @@ TRAKNN_ERR_INVALID_ARG = -1
 TRAKNN_ERR_UNSUPPORTED = -2
 TRAKNN_ERR_WORKSPACE = -3
 TRAKNN_ERR_HIP = -4
+TRAKNN_ERR_SCRATCH_LIMIT = -5
+NOALLOC_MAX_BYTES = 32 << 20
 
 TRAKNN_FP32 = 0
 TRAKNN_BF16X3 = 1
@@ -39,7 +41,8 @@ MAX_L = 16
 MAX_K = 64
 STAGES = ("centre_stats", "centre_convert", "gram", "window_topk", "merge")
 
-EXPORTS = ("traknn_plan", "traknn_plan_destroy", "traknn_knn", "traknn_score",
+EXPORTS = ("traknn_plan", "traknn_plan_destroy", "traknn_knn", "traknn_knn_noalloc",
+           "traknn_score",
            "traknn_score_prefix", "traknn_local_dim", "traknn_score_backward",
            "traknn_backward_workspace", "traknn_status_string", "traknn_set_timing",
            "traknn_stage_times")
@@ -71,6 +74,7 @@ def _load() -> ctypes.CDLL:
                                 ctypes.POINTER(sz)]
     lib.traknn_plan_destroy.argtypes = [vp]
     lib.traknn_knn.argtypes = [vp, vp, i64, vp, sz, vp, vp, vp]
+    lib.traknn_knn_noalloc.argtypes = [vp, vp, i64, vp, vp, vp]
     lib.traknn_score.argtypes = [vp, vp, vp, vp]
     lib.traknn_score_prefix.argtypes = [vp, vp, vp, vp]
     lib.traknn_local_dim.argtypes = [vp, vp, vp, vp]
@@ -167,6 +171,11 @@ def traknn_knn(plan, X, ldx: int, ws, ws_bytes: int, nbr_idx, nbr_dist,
                stream=None) -> None:
     _ck(_lib.traknn_knn(plan, _ptr(X), int(ldx), _ptr(ws), int(ws_bytes),
                         _ptr(nbr_idx), _ptr(nbr_dist), _stream(stream)), "traknn_knn")
+
+
+def traknn_knn_noalloc(plan, X, ldx: int, nbr_idx, nbr_dist, stream=None) -> None:
+    _ck(_lib.traknn_knn_noalloc(plan, _ptr(X), int(ldx), _ptr(nbr_idx), _ptr(nbr_dist),
+                                _stream(stream)), "traknn_knn_noalloc")
 
 
 def traknn_score(plan, nbr_dist, scores, stream=None) -> None:
