@@ -248,6 +248,61 @@ def time_small_d(tk, torch, synth, steps, warmup):
     return out
 
 
+def time_mode(tk, torch, Xn, L, k, prec, mode, steps, warmup):
+    """ms per knn call (and the stage split) of one mode and precision."""
+    X = torch.from_numpy(Xn).cuda()
+    p = tk.Plan(Xn.shape[0], Xn.shape[1], L, L, k, prec, mode=mode)
+    idx, dist = p.empty_outputs()
+    for _ in range(warmup):
+        p.knn(X, idx, dist)
+    torch.cuda.synchronize()
+    p.set_timing(True)
+    st = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        p.knn(X, idx, dist)
+        st.append(p.stage_times())
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    p.set_timing(False)
+    out = {"mode": mode, "prec": prec, "ms_per_call": ms,
+           "pairs_per_s": float(Xn.shape[0] - L + 1) ** 2 / (ms * 1e-3),
+           "stage_ms": {q: round(float(np.mean([s[q] for s in st])), 4) for q in st[0]},
+           "workspace_GiB": p.ws_bytes / 2 ** 30}
+    res = (idx[0].cpu().numpy(), dist[0].cpu().numpy())
+    p.close()
+    del X, idx, dist
+    torch.cuda.empty_cache()
+    return out, res
+
+
+def time_fused(tk, torch, synth, Xfull, w, steps, warmup):
+    """The fused (S-free) mode beside the matrix mode: the headline workload
+    in BF16x3 (and whether its lists and distances equal the matrix mode's
+    bit for bit), and the small-D shapes of the PCA comparison (a 4 x 8 grid
+    and the full workload's 13 leading principal components) at k = 10 and
+    40, where the fused mode also runs in FP64."""
+    out = {}
+    m, rm = time_mode(tk, torch, Xfull, w.L, w.k, "bf16x3", "matrix", steps, warmup)
+    f, rf = time_mode(tk, torch, Xfull, w.L, w.k, "bf16x3", "fused", steps, warmup)
+    f["equal_to_matrix_mode"] = bool(np.array_equal(rm[0], rf[0]) and np.array_equal(rm[1], rf[1]))
+    out["headline"] = {"shape": f"T={w.T}, D={w.D}, L={w.L}, k={w.k}", "matrix": m, "fused": f}
+    log(f"[bench] fused headline: matrix {m['ms_per_call']:.2f} ms, fused {f['ms_per_call']:.2f} ms")
+    g32, _ = synth.make_fields(w.T, 4, 8, sigma=1.0, n_events=20, event_len=5, seed=4)
+    pca, _, frac = synth.make_pca_workload(13)
+    for name, Xn in (("grid 4x8 (D=32)", g32), ("PCA 13 (D=13)", pca)):
+        for k in (10, 40):
+            row = {}
+            for prec, mode in (("bf16x3", "matrix"), ("bf16x3", "fused"), ("fp64", "fused")):
+                row[f"{prec}_{mode}"] = time_mode(tk, torch, Xn, w.L, k, prec, mode, steps,
+                                                  warmup)[0]
+            out[f"{name}, k={k}"] = row
+            log(f"[bench] fused {name} k={k}: " + ", ".join(
+                f"{q} {v['ms_per_call']:.2f} ms" for q, v in row.items()))
+    out["pca13_explained_variance"] = frac
+    return out
+
+
 def time_backward(tk, torch, synth, steps):
     """The differentiation configuration: T = 10957 daily 64 x 128 fields,
     L = 5, k = 10, FP32 forward, then the backward of the summed score of the
@@ -376,6 +431,8 @@ def main():
     ap.add_argument("--only", default=None, help="time one precision only")
     ap.add_argument("--sweep-rows", type=int, default=64,
                     help="oracle rows per length checked for the all-lengths sweep (0 = skip)")
+    ap.add_argument("--no-fused", action="store_true",
+                    help="skip the fused-mode comparison")
     ap.add_argument("--no-backward", action="store_true",
                     help="skip the backward timing (T = 10957 configuration)")
     ap.add_argument("--scaling", action="store_true",
@@ -474,6 +531,11 @@ def main():
         small = time_small_d(tk, torch, synth, args.compare_steps, args.warmup)
         log(f"[bench] small D: {small}")
 
+    fused = None
+    if not args.only and not args.no_fused:
+        log("[bench] timing the fused (S-free) mode beside the matrix mode")
+        fused = time_fused(tk, torch, synth, Xn, w, args.compare_steps, args.warmup)
+
     bwd = None
     if not args.no_backward and not args.only:
         log("[bench] timing the backward configuration")
@@ -541,6 +603,7 @@ def main():
         "band_mode": band,
         "sweep": sweep,
         "small_d": small,
+        "fused": fused,
         "backward": bwd,
         "parity_sample": par,
         "planted_in_top40": f"{planted_found}/{len(starts)}",

@@ -100,7 +100,7 @@ bool plan_window(traknn_plan_s* p) {
 // Fused mode: tile stride, block-rows and the establishing offsets (the
 // diagonal band of tiles plus far offsets, as many as keep the establishing
 // launch within about one round of the GPU: every row then meets a few
-// hundred candidates there), and the per-row candidate capacity.
+// hundred candidates there).
 void plan_fused(traknn_plan_s* p) {
   const traknn_config& c = p->cfg;
   FusedGeom& g = p->fg;
@@ -136,8 +136,6 @@ void plan_fused(traknn_plan_s* p) {
     const int64_t need = (int64_t)(g.nbt - 1) * g.B + GRAM_TILE;
     if (need > p->Tpad) p->Tpad = round_up(need, GRAM_TILE);
   }
-  const int64_t cap = (int64_t)c.k * 64 > 1024 ? (int64_t)c.k * 64 : 1024;
-  p->fcap = (int)(cap < p->np0 ? cap : p->np0);
 }
 
 void plan_layout(traknn_plan_s* p) {
@@ -162,10 +160,11 @@ void plan_layout(traknn_plan_s* p) {
     const bool mfma = prec != TRAKNN_FP64;
     L.ncs = take(mfma ? (size_t)norm_chunks(p->Dpad) * p->Tpad * sizeof(float) : 0);
     L.xc = take(mfma ? (size_t)p->Tpad * p->Dpad * elem_bytes(prec) : 0);
+    const size_t nslot = (size_t)p->fg.nbt + 1;
     L.f_bound = take(np * sizeof(double));
-    L.f_cnt = take(np * sizeof(int32_t));
-    L.f_bd = take(np * (size_t)p->fcap * sizeof(double));
-    L.f_bi = take(np * (size_t)p->fcap * sizeof(int32_t));
+    L.f_cnt = take(np * nslot * sizeof(int32_t));
+    L.f_sd = take(np * nslot * p->cfg.k * sizeof(double));
+    L.f_si = take(np * nslot * p->cfg.k * sizeof(int32_t));
     L.S = L.ST = L.part_d = L.part_i = L.cpart_d = L.cpart_i = o;
     L.total = o;
     return;
@@ -213,9 +212,10 @@ int record(traknn_plan_s* p, int slot, hipStream_t s) {
 namespace {
 
 // Fused mode after the centring: the establishing launch, each row's bound,
-// the filtering launch, then the select (and the exact recomputation of rows
-// whose candidate buffers overflowed). Timing slots: 3 after the fused tiles
-// and bounds, 4 after the select, 5 after the fallback.
+// the filtering launch, then the select. Every slot is written by its tile
+// on every call, so nothing needs clearing. Timing slots: 3 after the fused
+// tiles and bounds, 4 after the select (stage 4 of the matrix mode, the
+// merge, is empty).
 int enqueue_fused(traknn_plan_s* plan, const float* X, int64_t ldx, void* workspace,
                   int32_t* nbr_idx, double* nbr_dist, hipStream_t s) {
   const traknn_config& c = plan->cfg;
@@ -223,11 +223,10 @@ int enqueue_fused(traknn_plan_s* plan, const float* X, int64_t ldx, void* worksp
   const FusedGeom& g = plan->fg;
   const double* mu = at<double>(workspace, L.mu);
   double* bound = at<double>(workspace, L.f_bound);
-  const FusedOut out{at<int32_t>(workspace, L.f_cnt), at<double>(workspace, L.f_bd),
-                     at<int32_t>(workspace, L.f_bi), plan->fcap};
+  const FusedSlots out{at<int32_t>(workspace, L.f_cnt), at<double>(workspace, L.f_sd),
+                       at<int32_t>(workspace, L.f_si), g.nbt + 1, c.k};
   const int D = (int)plan->D;
   int rc;
-  if ((rc = fail_hip(launch_fused_clear(g, out, s)))) return rc;
   if (c.precision == TRAKNN_FP64) {
     if ((rc = fail_hip(launch_fused_f64(X, ldx, D, mu, g, true, bound, out, s)))) return rc;
     if ((rc = fail_hip(launch_fused_bound(g, out, bound, s)))) return rc;
@@ -244,8 +243,7 @@ int enqueue_fused(traknn_plan_s* plan, const float* X, int64_t ldx, void* worksp
       return rc;
   }
   if ((rc = record(plan, 3, s))) return rc;
-  if ((rc = fail_hip(launch_fused_select(X, ldx, D, mu, g, out, nbr_idx, nbr_dist, s))))
-    return rc;
+  if ((rc = fail_hip(launch_fused_select(g, out, nbr_idx, nbr_dist, s)))) return rc;
   if ((rc = record(plan, 4, s))) return rc;
   if ((rc = record(plan, 5, s))) return rc;
   if (plan->timing) plan->timed_calls++;

@@ -1,7 +1,7 @@
 // Fused S-free path (paper, Algorithm 1 stages 1-3 joined tile by tile, so the
 // T x T distance matrix is never stored; Section 7 names out-of-core
-// computation as future work) -- the FP64 tile kernel, the bound and select
-// kernels and the exact fallback shared with the MFMA-fused Gram.
+// computation as future work) -- the FP64 tile kernel, and the bound and
+// select kernels shared with the MFMA-fused Gram.
 //
 // FP64 precision: each tile evaluates Eq. 4, d = N_i + N_j - 2 <x_i, x_j>,
 // with FP64 operands (the FP32 fields shifted per cell by the FP64 sample
@@ -12,7 +12,7 @@
 // distance is a small fraction of its norms: the rounding error is about
 // 2^-53 N, far below any tolerance. The distance is then rounded once to
 // FP32, as the distance matrix of the other modes stores it, and the tile
-// walk (fused_walk.h) does the rest.
+// consumer (fused_walk.h) does the rest.
 #include "dist_clamp.h"
 #include "fused_walk.h"
 #include "internal.h"
@@ -63,13 +63,13 @@ __device__ __forceinline__ bool fused_tile(int64_t e, const FusedGeom& g, bool e
   return true;
 }
 
+
 template <bool ESTABLISH>
 __global__ __launch_bounds__(F64_THREADS) void fused_f64_kernel(
     const float* __restrict__ X, int64_t ldx, int D, const double* __restrict__ mu,
-    FusedGeom g, const double* __restrict__ bound, FusedOut out) {
+    FusedGeom g, const double* __restrict__ bound, FusedSlots out) {
   __shared__ __attribute__((aligned(16))) char un[F64_UNION_BYTES];
   __shared__ double nrm[2][F64_TILE];  // squared norms of the A and B rows
-  __shared__ double rbnd[2][F64_TILE];  // recipient bounds: rows, columns
   int I, J;
   if (!fused_tile(blockIdx.x, g, ESTABLISH, I, J)) return;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -100,7 +100,7 @@ __global__ __launch_bounds__(F64_THREADS) void fused_f64_kernel(
         nacc = __builtin_fma(x, x, nacc);
       }
     }
-#pragma unroll 2
+#pragma unroll 1
     for (int c = 0; c < F64_KC; ++c) {
       const double b0 = Bt[c * F64_BPITCH + lane];
       const double b1 = Bt[c * F64_BPITCH + lane + 64];
@@ -113,12 +113,6 @@ __global__ __launch_bounds__(F64_THREADS) void fused_f64_kernel(
     }
   }
   nrm[tid >> 7][tid & (F64_TILE - 1)] = nacc;
-  // recipient bounds of the tile's trajectory rows and columns
-  if constexpr (!ESTABLISH) {
-    const int side = tid >> 7, p = tid & (F64_TILE - 1);
-    const int64_t t = (side ? j0 : i0) + p;
-    rbnd[side][p] = (p < g.B && t < g.np) ? bound[t] : -1.0;
-  }
   __syncthreads();  // panels read, norms written
   float* V = (float*)un;  // [F64_TILE][F64_LD] snapshot distances of the tile
 #pragma unroll
@@ -131,61 +125,54 @@ __global__ __launch_bounds__(F64_THREADS) void fused_f64_kernel(
     }
   }
   __syncthreads();
-  // Row walk (recipients = rows, waves 0-1) and column walk (recipients =
-  // columns, waves 2-3); each group of two waves has 128 lanes >= B.
-  const int grp = w >> 1, l = (w & 1) * 64 + lane;
-  if constexpr (ESTABLISH) {
-    if (grp == 0)
-      tile_establish(V, F64_LD, 1, g.B, 0, g.B, (int)i0, (int)j0, 1, g.L, g.np, g.k, w & 1, 2,
-                     lane, out);
-    else
-      tile_establish(V, 1, F64_LD, g.B, 0, g.B, (int)j0, (int)i0, -1, g.L, g.np, g.k, w & 1, 2,
-                     lane, out);
-  } else {
-    if (grp == 0)
-      tile_walk(V, F64_LD, 1, g.B, 0, g.B, (int)i0, (int)j0, 1, g.L, g.np, g.k, rbnd[0], l,
-                lane, out);
-    else
-      tile_walk(V, 1, F64_LD, g.B, 0, g.B, (int)j0, (int)i0, -1, g.L, g.np, g.k, rbnd[1], l,
-                lane, out);
-  }
+  // The row side (recipients = the tile's rows, slot J + 1) on waves 0-1 and
+  // the column side (recipients = its columns, slot I) on waves 2-3.
+  const int side = w >> 1;
+  side_topk<TRAKNN_MAX_L>(V, side ? 1 : F64_LD, side ? F64_LD : 1, g.B, g.B,
+                          (int)(side ? j0 : i0), (int)(side ? i0 : j0), side ? -1 : 1,
+                          side ? I : J + 1, g.L, g.np, w & 1, 2, lane,
+                          ESTABLISH ? nullptr : bound, out);
 }
 
-__global__ __launch_bounds__(256) void fill_i32(int32_t* p, int64_t n, int32_t v) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i < n) p[i] = v;
-}
-
-// One wave per row: the k smallest (distance, index) of the row's appended
-// entries, in a lane-resident list (first chunk sorted, later chunks
-// ballot-filtered against the list's k-th and inserted). FINAL writes the
-// neighbour list (rows whose buffer overflowed are left to the fallback);
-// otherwise the row's bound, the k-th distance (+inf with fewer than k).
+// One wave per row: the k nearest over the row's slots -- every slot (FINAL,
+// the neighbour list), or only those of the establishing tiles (the bound:
+// the k-th distance, +inf when they hold fewer than k). Lane u takes slot
+// c0 + u of each batch of 64 and offers its entries one at a time, so a
+// ballot filters 64 candidates against the list's k-th at once.
 template <bool FINAL>
-__global__ __launch_bounds__(256) void select_kernel(FusedOut out, int np, int k,
+__global__ __launch_bounds__(256) void select_kernel(FusedGeom g, FusedSlots out,
                                                      double* __restrict__ bound,
                                                      int32_t* __restrict__ idx,
                                                      double* __restrict__ dist) {
   const int lane = threadIdx.x & 63;
-  const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (t >= np) return;
-  const int total = out.cnt[t];
-  if (FINAL && total > out.cap) return;
-  const int n = total < out.cap ? total : out.cap;
-  const double* bd = out.bd + t * out.cap;
-  const int32_t* bi = out.bi + t * out.cap;
+  const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (t >= g.np) return;
+  const int k = out.k;
+  const int It = t / g.B;
+  // the establishing slots: tiles (It - h, It) (column side, slot It - h) and
+  // (It, It + h) (row side, slot It + h + 1) for the offsets h
+  const int nsel = FINAL ? out.nslot : 2 * g.nh;
   double ed = __builtin_huge_val();
   int ei = INT_MAX;
-  for (int c0 = 0; c0 < n; c0 += 64) {
-    const bool in = c0 + lane < n;
-    double d = in ? bd[c0 + lane] : __builtin_huge_val();
-    int c = in ? bi[c0 + lane] : INT_MAX - 64 + lane;
-    if (c0 == 0) {
-      // lane r now holds the r-th smallest entry; lanes from n on the padding
-      bitonic_sort64(d, c, lane);
-      ed = lane < n ? d : __builtin_huge_val();
-      ei = lane < n ? c : INT_MAX;
-    } else {
+  for (int c0 = 0; c0 < nsel; c0 += 64) {
+    const int u = c0 + lane;
+    int slot = -1;
+    if (u < nsel) {
+      if (FINAL) {
+        slot = u;
+      } else {
+        const int h = g.h[u >> 1];
+        slot = (u & 1) ? (It + h < g.nbt ? It + h + 1 : -1) : (It - h >= 0 ? It - h : -1);
+      }
+    }
+    const int64_t base = (int64_t)t * out.nslot + (slot < 0 ? 0 : slot);
+    const int n = slot < 0 ? 0 : out.cnt[base];
+    int nmax = n;
+    for (int o = 32; o > 0; o >>= 1) nmax = max(nmax, __shfl_xor(nmax, o, 64));
+    for (int e = 0; e < nmax; ++e) {
+      const bool in = e < n;
+      const double d = in ? out.d[base * k + e] : __builtin_huge_val();
+      const int c = in ? out.i[base * k + e] : INT_MAX;
       const double kd = readlane_d(ed, k - 1);
       const int ki = __builtin_amdgcn_readlane(ei, k - 1);
       const bool pass = in && key_less(d, c, kd, ki);
@@ -195,80 +182,11 @@ __global__ __launch_bounds__(256) void select_kernel(FusedOut out, int np, int k
   }
   if (FINAL) {
     if (lane < k) {
-      idx[t * k + lane] = lane < n ? ei : -1;
-      dist[t * k + lane] = lane < n ? ed : __builtin_huge_val();
+      idx[(int64_t)t * k + lane] = ei == INT_MAX ? -1 : ei;
+      dist[(int64_t)t * k + lane] = ed;
     }
   } else if (lane == 0) {
-    bound[t] = n >= k ? readlane_d(ed, k - 1) : __builtin_huge_val();
-  }
-}
-
-// Exact recomputation of the rows whose buffer overflowed (pathological data:
-// many candidates tied at a row's bound). One workgroup per row; D_L(t, j) of
-// every candidate from the fields in FP64 (Eq. 4, products and sums in
-// increasing cell order, exactly as the FP64 tiles form them), rounded to
-// FP32 per snapshot pair as the tiles store them and summed over m in FP64.
-// Each wave keeps a lane-resident list over its share of the candidates; wave
-// 0 then merges the four lists.
-__global__ __launch_bounds__(256) void fallback_kernel(const float* __restrict__ X, int64_t ldx,
-                                                       int D, const double* __restrict__ mu,
-                                                       FusedGeom g, FusedOut out,
-                                                       int32_t* __restrict__ idx,
-                                                       double* __restrict__ dist) {
-  const int t = blockIdx.x;
-  if (t >= g.np || out.cnt[t] <= out.cap) return;
-  __shared__ double ld_d[4][64];
-  __shared__ int ld_i[4][64];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int L = g.L, k = g.k;
-  auto norm = [&](int64_t r) {
-    double s = 0.0;
-    for (int p = 0; p < D; ++p) {
-      const double x = centred(X, ldx, g.T, D, mu, r, p);
-      s = __builtin_fma(x, x, s);
-    }
-    return s;
-  };
-  double ed = __builtin_huge_val();
-  int ei = INT_MAX;
-  for (int j0 = w * 64; j0 < g.np; j0 += 256) {
-    const int j = j0 + lane;
-    const bool valid = j < g.np && (j - t >= L || t - j >= L);
-    double Dl = 0.0;
-    if (j < g.np) {
-      for (int m = 0; m < L; ++m) {
-        const int64_t a = t + m, b = j + m;
-        double gab = 0.0;
-        for (int p = 0; p < D; ++p)
-          gab = __builtin_fma(centred(X, ldx, g.T, D, mu, a, p),
-                              centred(X, ldx, g.T, D, mu, b, p), gab);
-        // the pair as the tiles evaluate it: the smaller field on the A side
-        const double v = a < b ? f64_dist(norm(a), norm(b), gab) : f64_dist(norm(b), norm(a), gab);
-        Dl += (double)clamp_distance((float)v);
-      }
-    }
-    const double kd = readlane_d(ed, k - 1);
-    const int ki = __builtin_amdgcn_readlane(ei, k - 1);
-    const bool pass = valid && key_less(Dl, j, kd, ki);
-    const uint64_t m = __ballot(pass);
-    if (m) insert_reg(m, Dl, j, k, ed, ei);
-  }
-  ld_d[w][lane] = ed;
-  ld_i[w][lane] = ei;
-  __syncthreads();
-  if (w != 0) return;
-  for (int u = 1; u < 4; ++u) {
-    const double d = lane < k ? ld_d[u][lane] : __builtin_huge_val();
-    const int c = lane < k ? ld_i[u][lane] : INT_MAX;
-    const double kd = readlane_d(ed, k - 1);
-    const int ki = __builtin_amdgcn_readlane(ei, k - 1);
-    const bool pass = lane < k && c != INT_MAX && key_less(d, c, kd, ki);
-    const uint64_t m = __ballot(pass);
-    if (m) insert_reg(m, d, c, k, ed, ei);
-  }
-  if (lane < k) {
-    idx[(int64_t)t * k + lane] = ei == INT_MAX ? -1 : ei;
-    dist[(int64_t)t * k + lane] = ed;
+    bound[t] = readlane_d(ed, k - 1);
   }
 }
 
@@ -280,15 +198,9 @@ int64_t fused_establish_tiles(const FusedGeom& g) {
   return n;
 }
 
-hipError_t launch_fused_clear(const FusedGeom& g, const FusedOut& out, hipStream_t s) {
-  hipLaunchKernelGGL(fill_i32, dim3((unsigned)((g.np + 255) / 256)), dim3(256), 0, s, out.cnt,
-                     (int64_t)g.np, 0);
-  return hipGetLastError();
-}
-
 hipError_t launch_fused_f64(const float* X, int64_t ldx, int D, const double* mu,
                             const FusedGeom& g, bool establish, const double* bound,
-                            const FusedOut& out, hipStream_t s) {
+                            const FusedSlots& out, hipStream_t s) {
   const int64_t ntiles = establish ? fused_establish_tiles(g)
                                    : (int64_t)g.nbt * (g.nbt + 1) / 2;
   if (ntiles <= 0) return hipSuccess;
@@ -301,22 +213,17 @@ hipError_t launch_fused_f64(const float* X, int64_t ldx, int D, const double* mu
   return hipGetLastError();
 }
 
-hipError_t launch_fused_bound(const FusedGeom& g, const FusedOut& out, double* bound,
+hipError_t launch_fused_bound(const FusedGeom& g, const FusedSlots& out, double* bound,
                               hipStream_t s) {
-  hipLaunchKernelGGL(select_kernel<false>, dim3((unsigned)((g.np + 3) / 4)), dim3(256), 0, s, out,
-                     g.np, g.k, bound, nullptr, nullptr);
+  hipLaunchKernelGGL(select_kernel<false>, dim3((unsigned)((g.np + 3) / 4)), dim3(256), 0, s, g,
+                     out, bound, nullptr, nullptr);
   return hipGetLastError();
 }
 
-hipError_t launch_fused_select(const float* X, int64_t ldx, int D, const double* mu,
-                               const FusedGeom& g, const FusedOut& out, int32_t* idx,
+hipError_t launch_fused_select(const FusedGeom& g, const FusedSlots& out, int32_t* idx,
                                double* dist, hipStream_t s) {
-  hipLaunchKernelGGL(select_kernel<true>, dim3((unsigned)((g.np + 3) / 4)), dim3(256), 0, s, out,
-                     g.np, g.k, nullptr, idx, dist);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(fallback_kernel, dim3((unsigned)g.np), dim3(256), 0, s, X, ldx, D, mu, g,
-                     out, idx, dist);
+  hipLaunchKernelGGL(select_kernel<true>, dim3((unsigned)((g.np + 3) / 4)), dim3(256), 0, s, g,
+                     out, nullptr, idx, dist);
   return hipGetLastError();
 }
 

