@@ -136,24 +136,32 @@ __global__ __launch_bounds__(F64_THREADS) void fused_f64_kernel(
 
 // One wave per row: the k nearest over the row's slots -- every slot (FINAL,
 // the neighbour list), or only those of the establishing tiles (the bound:
-// the k-th distance, +inf when they hold fewer than k). Lane u takes slot
-// c0 + u of each batch of 64 and offers its entries one at a time, so a
-// ballot filters 64 candidates against the list's k-th at once.
+// the k-th distance, +inf when they hold fewer than k). Slots come 64 at a
+// time (lane = slot): one load of their counts, a wave prefix sum, and the
+// entries' positions parked in LDS (up to SEL_PARK at a time), so that each
+// lane then loads one entry and a ballot filters 64 entries against the
+// list's k-th at once -- two memory round trips per batch of slots.
+constexpr int SEL_WAVES = 4;
+constexpr int SEL_PARK = 1024;
 template <bool FINAL>
-__global__ __launch_bounds__(256) void select_kernel(FusedGeom g, FusedSlots out,
-                                                     double* __restrict__ bound,
-                                                     int32_t* __restrict__ idx,
-                                                     double* __restrict__ dist) {
+__global__ __launch_bounds__(64 * SEL_WAVES) void select_kernel(FusedGeom g, FusedSlots out,
+                                                               double* __restrict__ bound,
+                                                               int32_t* __restrict__ idx,
+                                                               double* __restrict__ dist) {
+  __shared__ int park[SEL_WAVES][SEL_PARK];  // (slot << 6 | entry) per entry
   const int lane = threadIdx.x & 63;
-  const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int w = threadIdx.x >> 6;
+  const int t = blockIdx.x * SEL_WAVES + w;
   if (t >= g.np) return;
   const int k = out.k;
   const int It = t / g.B;
+  int* mine = park[w];
   // the establishing slots: tiles (It - h, It) (column side, slot It - h) and
   // (It, It + h) (row side, slot It + h + 1) for the offsets h
   const int nsel = FINAL ? out.nslot : 2 * g.nh;
   double ed = __builtin_huge_val();
   int ei = INT_MAX;
+  const int64_t row0 = (int64_t)t * out.nslot;
   for (int c0 = 0; c0 < nsel; c0 += 64) {
     const int u = c0 + lane;
     int slot = -1;
@@ -165,19 +173,38 @@ __global__ __launch_bounds__(256) void select_kernel(FusedGeom g, FusedSlots out
         slot = (u & 1) ? (It + h < g.nbt ? It + h + 1 : -1) : (It - h >= 0 ? It - h : -1);
       }
     }
-    const int64_t base = (int64_t)t * out.nslot + (slot < 0 ? 0 : slot);
-    const int n = slot < 0 ? 0 : out.cnt[base];
-    int nmax = n;
-    for (int o = 32; o > 0; o >>= 1) nmax = max(nmax, __shfl_xor(nmax, o, 64));
-    for (int e = 0; e < nmax; ++e) {
-      const bool in = e < n;
-      const double d = in ? out.d[base * k + e] : __builtin_huge_val();
-      const int c = in ? out.i[base * k + e] : INT_MAX;
-      const double kd = readlane_d(ed, k - 1);
-      const int ki = __builtin_amdgcn_readlane(ei, k - 1);
-      const bool pass = in && key_less(d, c, kd, ki);
-      const uint64_t m = __ballot(pass);
-      if (m) insert_reg(m, d, c, k, ed, ei);
+    const int n = slot < 0 ? 0 : out.cnt[row0 + slot];
+    // inclusive prefix sum of the counts over the lanes
+    int incl = n;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += y;
+    }
+    const int total = __builtin_amdgcn_readlane(incl, 63);
+    for (int p0 = 0; p0 < total; p0 += SEL_PARK) {
+      // entries p0 .. p0 + SEL_PARK - 1 of the batch, in lane (slot) order
+      const int p1 = p0 + SEL_PARK < total ? p0 + SEL_PARK : total;
+      const int qlo = p0 - (incl - n) > 0 ? p0 - (incl - n) : 0;
+      const int qhi = p1 - (incl - n) < n ? p1 - (incl - n) : n;
+      for (int q = qlo; q < qhi; ++q) mine[incl - n + q - p0] = (slot << 6) | q;
+      __builtin_amdgcn_wave_barrier();
+      for (int b0 = p0; b0 < p1; b0 += 64) {
+        const int e = b0 + lane;
+        double d = __builtin_huge_val();
+        int c = INT_MAX;
+        if (e < p1) {
+          const int pk = mine[e - p0];
+          const int64_t at = (row0 + (pk >> 6)) * k + (pk & 63);
+          d = out.d[at];
+          c = out.i[at];
+        }
+        const double kd = readlane_d(ed, k - 1);
+        const int ki = __builtin_amdgcn_readlane(ei, k - 1);
+        const uint64_t m = __ballot(e < p1 && key_less(d, c, kd, ki));
+        if (m) insert_reg(m, d, c, k, ed, ei);
+      }
+      __builtin_amdgcn_wave_barrier();
     }
   }
   if (FINAL) {
@@ -215,15 +242,17 @@ hipError_t launch_fused_f64(const float* X, int64_t ldx, int D, const double* mu
 
 hipError_t launch_fused_bound(const FusedGeom& g, const FusedSlots& out, double* bound,
                               hipStream_t s) {
-  hipLaunchKernelGGL(select_kernel<false>, dim3((unsigned)((g.np + 3) / 4)), dim3(256), 0, s, g,
-                     out, bound, nullptr, nullptr);
+  const dim3 grid((unsigned)((g.np + SEL_WAVES - 1) / SEL_WAVES));
+  hipLaunchKernelGGL(select_kernel<false>, grid, dim3(64 * SEL_WAVES), 0, s, g, out, bound,
+                     nullptr, nullptr);
   return hipGetLastError();
 }
 
 hipError_t launch_fused_select(const FusedGeom& g, const FusedSlots& out, int32_t* idx,
                                double* dist, hipStream_t s) {
-  hipLaunchKernelGGL(select_kernel<true>, dim3((unsigned)((g.np + 3) / 4)), dim3(256), 0, s, g,
-                     out, nullptr, idx, dist);
+  const dim3 grid((unsigned)((g.np + SEL_WAVES - 1) / SEL_WAVES));
+  hipLaunchKernelGGL(select_kernel<true>, grid, dim3(64 * SEL_WAVES), 0, s, g, out, nullptr,
+                     idx, dist);
   return hipGetLastError();
 }
 
