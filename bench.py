@@ -303,6 +303,30 @@ def time_fused(tk, torch, synth, Xfull, w, steps, warmup):
     return out
 
 
+def time_vendor_gemm(torch, T, D, steps):
+    """torch.matmul (hipBLASLt) in BF16 on the Gram's shape padded to whole
+    256-row tiles, the full square (2 n^2 D flop): the vendor's rate for a
+    plain GEMM of this size, beside which the Gram's counters are read."""
+    n = -(-T // 256) * 256
+    g = torch.Generator(device="cuda").manual_seed(0)
+    a = torch.randn(n, D, dtype=torch.bfloat16, device="cuda", generator=g)
+    b = a.t().contiguous()
+    c = torch.matmul(a, b)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        torch.matmul(a, b, out=c)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    out = {"shape": f"[{n} x {D}] @ [{D} x {n}], bf16 in and out", "ms": ms,
+           "tflops": 2.0 * n * n * D / (ms * 1e-3) / 1e12}
+    del a, b, c
+    torch.cuda.empty_cache()
+    return out
+
+
 def time_backward(tk, torch, synth, steps):
     """The differentiation configuration: T = 10957 daily 64 x 128 fields,
     L = 5, k = 10, FP32 forward, then the backward of the summed score of the
@@ -442,6 +466,9 @@ def main():
                          "this many rows, BF16x3 (0 = skip)")
     ap.add_argument("--calibrate-copy-gib", type=float, default=0.0,
                     help="also run a plain device copy of this many GiB (counter scale)")
+    ap.add_argument("--vendor-gemm", action="store_true",
+                    help="also time the vendor BF16 GEMM (torch.matmul) on the Gram's "
+                         "square shape, as a reference for the Gram's counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU: the library has no multi-GPU path "
@@ -491,6 +518,11 @@ def main():
             f"{r['pairs_per_s']:.3e} pairs/s, stages {r['stage_ms']}, "
             f"gram {r['gram_tflops']:.1f} TFLOP/s")
         results[prec] = r
+
+    vendor = None
+    if args.vendor_gemm:
+        vendor = time_vendor_gemm(torch, w.T, w.D, max(args.compare_steps, 3))
+        log(f"[bench] vendor GEMM: {vendor}")
 
     band = None
     if args.band_rows > 0 and not args.only:
@@ -604,6 +636,7 @@ def main():
         "sweep": sweep,
         "small_d": small,
         "fused": fused,
+        "vendor_gemm": vendor,
         "backward": bwd,
         "parity_sample": par,
         "planted_in_top40": f"{planted_found}/{len(starts)}",

@@ -92,18 +92,21 @@ extern "C" {
  *   TRAKNN_MODE_FUSED  : S-free. Each tile of the upper triangle (tiles overlap
  *                        by L - 1 fields, so every trajectory pair of a tile has
  *                        its L terms inside it) forms its trajectory distances
- *                        in LDS and offers every pair to both of its rows; only
- *                        candidates within a row's bound reach HBM. The bound of
- *                        each row is the k-th distance over a first launch on a
- *                        band of tiles that gives every row a few hundred
- *                        candidates, and the final k come from a select over
- *                        the rest. A row whose buffer of candidates overflows
- *                        (many candidates tied at its bound) is recomputed
- *                        exactly in FP64 from the fields. Single length only
- *                        (L_min == L_max), row_batch 0; precisions FP64 (vector
- *                        FP64 tiles of 128 fields) and FP32 / BF16X3 / FP16
- *                        (the MFMA Gram of 256 fields with the walk in its
- *                        epilogue). */
+ *                        in LDS and offers every pair to both of its rows; each
+ *                        (row, tile side) keeps at most k candidates within the
+ *                        row's bound in a slot of its own, so only those reach
+ *                        HBM. The bound of each row is the k-th distance over a
+ *                        first launch on a band of tiles that gives every row a
+ *                        few hundred candidates, and the final k come from a
+ *                        select over the row's slots. The MFMA precisions form
+ *                        every distance as the matrix mode does, so their lists
+ *                        equal its lists wherever its FP64 window recurrence is
+ *                        exact (distances whose exponents span fewer than about
+ *                        29 bits). Single length
+ *                        only (L_min == L_max), row_batch 0; precisions FP64
+ *                        (vector FP64 tiles of 128 fields) and FP32 / BF16X3 /
+ *                        FP16 (the MFMA Gram of 256 fields with the tile consumer
+ *                        in its epilogue). */
 #define TRAKNN_MODE_MATRIX 0
 #define TRAKNN_MODE_FUSED 1
 
