@@ -43,6 +43,9 @@ __global__ __launch_bounds__(256) void rev_count_kernel(
 }
 
 // Exclusive scan of cnt[0..n) into ptr[0..n], one workgroup of 1024 threads.
+// Each thread sums its run of counts SCAN_BATCH loads at a time, the loads of
+// a batch in flight together.
+constexpr int SCAN_BATCH = 16;
 __global__ __launch_bounds__(1024) void scan_kernel(const int32_t* __restrict__ cnt,
                                                     int n, int32_t* __restrict__ ptr) {
   __shared__ int32_t part[1024];
@@ -51,7 +54,13 @@ __global__ __launch_bounds__(1024) void scan_kernel(const int32_t* __restrict__ 
   const int b = tid * per;
   const int e = b + per < n ? b + per : n;
   int32_t s = 0;
-  for (int i = b; i < e; ++i) s += cnt[i];
+  for (int i0 = b; i0 < e; i0 += SCAN_BATCH) {
+    int32_t v[SCAN_BATCH];
+#pragma unroll
+    for (int u = 0; u < SCAN_BATCH; ++u) v[u] = i0 + u < e ? cnt[i0 + u] : 0;
+#pragma unroll
+    for (int u = 0; u < SCAN_BATCH; ++u) s += v[u];
+  }
   part[tid] = s;
   __syncthreads();
   for (int off = 1; off < 1024; off <<= 1) {
@@ -61,9 +70,15 @@ __global__ __launch_bounds__(1024) void scan_kernel(const int32_t* __restrict__ 
     __syncthreads();
   }
   int32_t run = tid > 0 ? part[tid - 1] : 0;
-  for (int i = b; i < e; ++i) {
-    ptr[i] = run;
-    run += cnt[i];
+  for (int i0 = b; i0 < e; i0 += SCAN_BATCH) {
+    int32_t v[SCAN_BATCH];
+#pragma unroll
+    for (int u = 0; u < SCAN_BATCH; ++u) v[u] = i0 + u < e ? cnt[i0 + u] : 0;
+#pragma unroll
+    for (int u = 0; u < SCAN_BATCH; ++u) {
+      if (i0 + u < e) ptr[i0 + u] = run;
+      run += v[u];
+    }
   }
   if (tid == 1023) ptr[n] = part[1023];
 }
