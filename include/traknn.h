@@ -95,10 +95,12 @@ extern "C" {
  *                        in LDS and offers every pair to both of its rows; each
  *                        (row, tile side) keeps at most k candidates within the
  *                        row's bound in a slot of its own, so only those reach
- *                        HBM. The bound of each row is the k-th distance over a
- *                        first launch on a band of tiles that gives every row a
- *                        few hundred candidates, and the final k come from a
- *                        select over the row's slots. The MFMA precisions form
+ *                        HBM. Tiles run in rounds of growing distance from
+ *                        the diagonal; after each round a refresh merges a
+ *                        row's slots into its running list, whose k-th is the
+ *                        row's bound in the next round, and the final k come
+ *                        from a select over the running list and the last
+ *                        round's slots. The MFMA precisions form
  *                        every distance as the matrix mode does, so their lists
  *                        equal its lists wherever its FP64 window recurrence is
  *                        exact (distances whose exponents span fewer than about

@@ -97,10 +97,8 @@ bool plan_window(traknn_plan_s* p) {
   return p->win_splits > 0 && (!p->rb || p->col_splits > 0);
 }
 
-// Fused mode: tile stride, block-rows and the establishing offsets (the
-// diagonal band of tiles plus far offsets, as many as keep the establishing
-// launch within about one round of the GPU: every row then meets a few
-// hundred candidates there).
+// Fused mode: tile stride and block-rows (the rounds of offsets are set per
+// launch).
 void plan_fused(traknn_plan_s* p) {
   const traknn_config& c = p->cfg;
   FusedGeom& g = p->fg;
@@ -113,24 +111,7 @@ void plan_fused(traknn_plan_s* p) {
   g.B = tile - (c.L_max - 1);
   if (!f64) g.B = g.B / 4 * 4;  // 16-byte aligned chunk-norm loads of each panel
   g.nbt = (int)((g.np + g.B - 1) / g.B);
-  const int64_t round = f64 ? 2 * 256 : 256;  // tiles the GPU runs at once
-  g.nh = 0;
-  g.h[g.nh++] = 0;
-  int64_t count = g.nbt;
-  if (g.nbt <= 4) {
-    for (int h = 1; h < g.nbt; ++h) g.h[g.nh++] = h;
-  } else {
-    const int num[7] = {1, 1, 3, 1, 3, 5, 7}, den[7] = {2, 4, 4, 8, 8, 8, 8};
-    for (int u = 0; u < 7 && g.nh < FUSED_MAX_OFFSETS; ++u) {
-      const int h = (int)(((int64_t)g.nbt * num[u] + den[u] - 1) / den[u]);
-      bool dup = h < 1 || h >= g.nbt;
-      for (int q = 0; q < g.nh && !dup; ++q) dup = g.h[q] == h;
-      if (dup || count + (g.nbt - h) > round) continue;
-      g.h[g.nh++] = h;
-      count += g.nbt - h;
-    }
-  }
-  for (int q = g.nh; q < FUSED_MAX_OFFSETS; ++q) g.h[q] = -1;
+  g.blo = g.bhi = 0;
   // the MFMA tiles read a full 256-row panel from every block-row's start
   if (!f64) {
     const int64_t need = (int64_t)(g.nbt - 1) * g.B + GRAM_TILE;
@@ -165,6 +146,8 @@ void plan_layout(traknn_plan_s* p) {
     L.f_cnt = take(np * nslot * sizeof(int32_t));
     L.f_sd = take(np * nslot * p->cfg.k * sizeof(double));
     L.f_si = take(np * nslot * p->cfg.k * sizeof(int32_t));
+    L.f_rd = take(np * p->cfg.k * sizeof(double));
+    L.f_ri = take(np * p->cfg.k * sizeof(int32_t));
     L.S = L.ST = L.part_d = L.part_i = L.cpart_d = L.cpart_i = o;
     L.total = o;
     return;
@@ -211,39 +194,53 @@ int record(traknn_plan_s* p, int slot, hipStream_t s) {
 
 namespace {
 
-// Fused mode after the centring: the establishing launch, each row's bound,
-// the filtering launch, then the select. Every slot is written by its tile
-// on every call, so nothing needs clearing. Timing slots: 3 after the fused
-// tiles and bounds, 4 after the select (stage 4 of the matrix mode, the
-// merge, is empty).
+// Fused mode after the centring: the rounds of tile offsets, the first
+// keeping each recipient's exact k nearest per tile, each later one only the
+// candidates within the rows' bounds; after every round but the last a
+// refresh merges its slots into the rows' running lists and sets their
+// bounds, and the final merge writes the lists. Every slot is written by its
+// tile on every call before it is read, so nothing needs clearing. Timing
+// slots: 3 after the rounds (their refreshes included), 4 after the final
+// merge (stage 4 of the matrix mode, the merge, is empty).
 int enqueue_fused(traknn_plan_s* plan, const float* X, int64_t ldx, void* workspace,
                   int32_t* nbr_idx, double* nbr_dist, hipStream_t s) {
   const traknn_config& c = plan->cfg;
   const Layout& L = plan->lay;
-  const FusedGeom& g = plan->fg;
+  FusedGeom g = plan->fg;
   const double* mu = at<double>(workspace, L.mu);
   double* bound = at<double>(workspace, L.f_bound);
+  double* run_d = at<double>(workspace, L.f_rd);
+  int32_t* run_i = at<int32_t>(workspace, L.f_ri);
   const FusedSlots out{at<int32_t>(workspace, L.f_cnt), at<double>(workspace, L.f_sd),
                        at<int32_t>(workspace, L.f_si), g.nbt + 1, c.k};
   const int D = (int)plan->D;
   int rc;
-  if (c.precision == TRAKNN_FP64) {
-    if ((rc = fail_hip(launch_fused_f64(X, ldx, D, mu, g, true, bound, out, s)))) return rc;
-    if ((rc = fail_hip(launch_fused_bound(g, out, bound, s)))) return rc;
-    if ((rc = fail_hip(launch_fused_f64(X, ldx, D, mu, g, false, bound, out, s)))) return rc;
-  } else {
-    const void* xc = at<char>(workspace, L.xc);
-    const float* ncs = at<float>(workspace, L.ncs);
-    if ((rc = fail_hip(launch_gram_fused(xc, ncs, plan->T, plan->Tpad, plan->Dpad, c.precision,
-                                         g, true, bound, out, s))))
+  int lo = 0;
+  for (int r = 0; r < FUSED_ROUNDS && lo < g.nbt; ++r) {
+    int hi = r + 1 < FUSED_ROUNDS ? FUSED_ROUND_END[r] : g.nbt;
+    if (hi > g.nbt) hi = g.nbt;
+    g.blo = lo;
+    g.bhi = hi;
+    const bool establish = r == 0;
+    if (c.precision == TRAKNN_FP64) {
+      if ((rc = fail_hip(launch_fused_f64(X, ldx, D, mu, g, establish, bound, out, s))))
+        return rc;
+    } else {
+      const void* xc = at<char>(workspace, L.xc);
+      const float* ncs = at<float>(workspace, L.ncs);
+      if ((rc = fail_hip(launch_gram_fused(xc, ncs, plan->T, plan->Tpad, plan->Dpad,
+                                           c.precision, g, establish, bound, out, s))))
+        return rc;
+    }
+    if (hi < g.nbt &&
+        (rc = fail_hip(launch_slots_refresh(g, out, bound, run_d, run_i, lo, hi, s))))
       return rc;
-    if ((rc = fail_hip(launch_fused_bound(g, out, bound, s)))) return rc;
-    if ((rc = fail_hip(launch_gram_fused(xc, ncs, plan->T, plan->Tpad, plan->Dpad, c.precision,
-                                         g, false, bound, out, s))))
-      return rc;
+    if (hi < g.nbt) lo = hi;
+    else break;
   }
   if ((rc = record(plan, 3, s))) return rc;
-  if ((rc = fail_hip(launch_fused_select(g, out, nbr_idx, nbr_dist, s)))) return rc;
+  if ((rc = fail_hip(launch_slots_final(g, out, run_d, run_i, lo, nbr_idx, nbr_dist, s))))
+    return rc;
   if ((rc = record(plan, 4, s))) return rc;
   if ((rc = record(plan, 5, s))) return rc;
   if (plan->timing) plan->timed_calls++;

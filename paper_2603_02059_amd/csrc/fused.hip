@@ -41,29 +41,6 @@ __device__ __forceinline__ double centred(const float* X, int64_t ldx, int T, in
   return (r < T && p < D) ? (double)X[r * ldx + p] - mu[p] : 0.0;
 }
 
-// Tile (I, J) of launch tile e: ESTABLISH enumerates the tiles (I, I + h) of
-// the offsets h of the geometry, I = 0 .. nbt - h - 1, offset by offset;
-// FILTER the whole upper triangle row by row, and reports the tiles of the
-// establishing set as skipped.
-__device__ __forceinline__ bool fused_tile(int64_t e, const FusedGeom& g, bool establish,
-                                           int& I, int& J) {
-  if (establish) return fused_establish_tile(e, g, I, J);
-  // row-major upper triangle: row I holds nbt - I tiles
-  int64_t u = e;
-  int i = 0;
-  while (i < g.nbt && u >= g.nbt - i) {
-    u -= g.nbt - i;
-    ++i;
-  }
-  if (i >= g.nbt) return false;
-  I = i;
-  J = i + (int)u;
-  for (int q = 0; q < g.nh; ++q)
-    if (J - I == g.h[q]) return false;  // done by the establishing launch
-  return true;
-}
-
-
 template <bool ESTABLISH>
 __global__ __launch_bounds__(F64_THREADS) void fused_f64_kernel(
     const float* __restrict__ X, int64_t ldx, int D, const double* __restrict__ mu,
@@ -71,7 +48,7 @@ __global__ __launch_bounds__(F64_THREADS) void fused_f64_kernel(
   __shared__ __attribute__((aligned(16))) char un[F64_UNION_BYTES];
   __shared__ double nrm[2][F64_TILE];  // squared norms of the A and B rows
   int I, J;
-  if (!fused_tile(blockIdx.x, g, ESTABLISH, I, J)) return;
+  if (!fused_band_tile(blockIdx.x, g, I, J)) return;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int64_t i0 = (int64_t)I * g.B, j0 = (int64_t)J * g.B;
   double* Ap = (double*)un;                    // [F64_TILE][F64_APITCH]
@@ -134,20 +111,26 @@ __global__ __launch_bounds__(F64_THREADS) void fused_f64_kernel(
                           ESTABLISH ? nullptr : bound, out);
 }
 
-// One wave per row: the k nearest over the row's slots -- every slot (FINAL,
-// the neighbour list), or only those of the establishing tiles (the bound:
-// the k-th distance, +inf when they hold fewer than k). Slots come 64 at a
-// time (lane = slot): one load of their counts, a wave prefix sum, and the
-// entries' positions parked in LDS (up to SEL_PARK at a time), so that each
-// lane then loads one entry and a ballot filters 64 entries against the
-// list's k-th at once -- two memory round trips per batch of slots.
+// One wave per row: the k nearest over some of the row's slots, starting
+// from the row's running list when there is one (hlo > 0). The slots are
+// those of the tiles whose offset J - I lies in [hlo, hhi): the column sides
+// of (It - h, It), slots It - h, and the row sides of (It, It + h), slots
+// It + h + 1, It the row's block-row. FINAL writes the neighbour list;
+// otherwise (a refresh) the list becomes the row's running list and its k-th
+// the row's bound (+inf while it holds fewer than k).
+//
+// Slots come 64 at a time (lane = slot): one load of their counts, a wave
+// prefix sum, and the entries' positions parked in LDS (up to SEL_PARK at a
+// time), so that each lane then loads one entry and a ballot filters 64
+// entries against the list's k-th at once -- two memory round trips per
+// batch of slots.
 constexpr int SEL_WAVES = 4;
 constexpr int SEL_PARK = 1024;
 template <bool FINAL>
-__global__ __launch_bounds__(64 * SEL_WAVES) void select_kernel(FusedGeom g, FusedSlots out,
-                                                               double* __restrict__ bound,
-                                                               int32_t* __restrict__ idx,
-                                                               double* __restrict__ dist) {
+__global__ __launch_bounds__(64 * SEL_WAVES) void select_kernel(
+    FusedGeom g, FusedSlots out, double* __restrict__ bound, double* __restrict__ run_d,
+    int32_t* __restrict__ run_i, int hlo, int hhi, int32_t* __restrict__ idx,
+    double* __restrict__ dist) {
   __shared__ int park[SEL_WAVES][SEL_PARK];  // (slot << 6 | entry) per entry
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
@@ -156,23 +139,22 @@ __global__ __launch_bounds__(64 * SEL_WAVES) void select_kernel(FusedGeom g, Fus
   const int k = out.k;
   const int It = t / g.B;
   int* mine = park[w];
-  // the establishing slots: tiles (It - h, It) (column side, slot It - h) and
-  // (It, It + h) (row side, slot It + h + 1) for the offsets h
-  const int nsel = FINAL ? out.nslot : 2 * g.nh;
+  // slot ranges: column sides It - hhi + 1 .. It - hlo, row sides
+  // It + hlo + 1 .. It + hhi, both cut to 0 .. nbt
+  const int clo = It - hhi + 1 > 0 ? It - hhi + 1 : 0, chi = It - hlo;
+  const int rlo = It + hlo + 1, rhi = It + hhi < g.nbt ? It + hhi : g.nbt;
+  const int ncol = chi >= clo ? chi - clo + 1 : 0, nrow = rhi >= rlo ? rhi - rlo + 1 : 0;
+  const int nsel = ncol + nrow;
   double ed = __builtin_huge_val();
   int ei = INT_MAX;
+  if (hlo > 0 && lane < k) {
+    ed = run_d[(int64_t)t * k + lane];
+    ei = run_i[(int64_t)t * k + lane];
+  }
   const int64_t row0 = (int64_t)t * out.nslot;
   for (int c0 = 0; c0 < nsel; c0 += 64) {
     const int u = c0 + lane;
-    int slot = -1;
-    if (u < nsel) {
-      if (FINAL) {
-        slot = u;
-      } else {
-        const int h = g.h[u >> 1];
-        slot = (u & 1) ? (It + h < g.nbt ? It + h + 1 : -1) : (It - h >= 0 ? It - h : -1);
-      }
-    }
+    const int slot = u >= nsel ? -1 : u < ncol ? clo + u : rlo + (u - ncol);
     const int n = slot < 0 ? 0 : out.cnt[row0 + slot];
     // inclusive prefix sum of the counts over the lanes
     int incl = n;
@@ -212,24 +194,29 @@ __global__ __launch_bounds__(64 * SEL_WAVES) void select_kernel(FusedGeom g, Fus
       idx[(int64_t)t * k + lane] = ei == INT_MAX ? -1 : ei;
       dist[(int64_t)t * k + lane] = ed;
     }
-  } else if (lane == 0) {
-    bound[t] = readlane_d(ed, k - 1);
+  } else {
+    if (lane < k) {
+      run_d[(int64_t)t * k + lane] = ed;
+      run_i[(int64_t)t * k + lane] = ei;
+    }
+    const double kth = readlane_d(ed, k - 1);
+    if (lane == 0) bound[t] = kth;
   }
 }
 
 }  // namespace
 
-int64_t fused_establish_tiles(const FusedGeom& g) {
+int64_t fused_band_tiles(const FusedGeom& g) {
+  const int hi = g.bhi < g.nbt ? g.bhi : g.nbt;
   int64_t n = 0;
-  for (int u = 0; u < g.nh; ++u) n += g.nbt - g.h[u];
+  for (int h = g.blo; h < hi; ++h) n += g.nbt - h;
   return n;
 }
 
 hipError_t launch_fused_f64(const float* X, int64_t ldx, int D, const double* mu,
                             const FusedGeom& g, bool establish, const double* bound,
                             const FusedSlots& out, hipStream_t s) {
-  const int64_t ntiles = establish ? fused_establish_tiles(g)
-                                   : (int64_t)g.nbt * (g.nbt + 1) / 2;
+  const int64_t ntiles = fused_band_tiles(g);
   if (ntiles <= 0) return hipSuccess;
   if (establish)
     hipLaunchKernelGGL(fused_f64_kernel<true>, dim3((unsigned)ntiles), dim3(F64_THREADS), 0, s,
@@ -240,18 +227,21 @@ hipError_t launch_fused_f64(const float* X, int64_t ldx, int D, const double* mu
   return hipGetLastError();
 }
 
-hipError_t launch_fused_bound(const FusedGeom& g, const FusedSlots& out, double* bound,
-                              hipStream_t s) {
+hipError_t launch_slots_refresh(const FusedGeom& g, const FusedSlots& out, double* bound,
+                                double* run_d, int32_t* run_i, int hlo, int hhi,
+                                hipStream_t s) {
   const dim3 grid((unsigned)((g.np + SEL_WAVES - 1) / SEL_WAVES));
   hipLaunchKernelGGL(select_kernel<false>, grid, dim3(64 * SEL_WAVES), 0, s, g, out, bound,
-                     nullptr, nullptr);
+                     run_d, run_i, hlo, hhi, nullptr, nullptr);
   return hipGetLastError();
 }
 
-hipError_t launch_fused_select(const FusedGeom& g, const FusedSlots& out, int32_t* idx,
-                               double* dist, hipStream_t s) {
+hipError_t launch_slots_final(const FusedGeom& g, const FusedSlots& out, const double* run_d,
+                              const int32_t* run_i, int hlo, int32_t* idx, double* dist,
+                              hipStream_t s) {
   const dim3 grid((unsigned)((g.np + SEL_WAVES - 1) / SEL_WAVES));
   hipLaunchKernelGGL(select_kernel<true>, grid, dim3(64 * SEL_WAVES), 0, s, g, out, nullptr,
+                     const_cast<double*>(run_d), const_cast<int32_t*>(run_i), hlo, g.nbt + 1,
                      idx, dist);
   return hipGetLastError();
 }

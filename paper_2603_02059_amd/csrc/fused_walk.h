@@ -20,11 +20,10 @@
 // nearest over a row's slots. Each recipient is handled by one wave (lane =
 // candidate), so its list lives in registers: nothing goes through atomics
 // and nothing can overflow.
-//  * ESTABLISH (a first launch over a band of tiles that gives every row a few
-//    hundred candidates): a recipient keeps its exact k nearest in the tile.
-//    A bound kernel then takes each row's k-th over these slots: an upper
-//    bound of its true k-th distance.
-//  * FILTER (every other tile): a recipient keeps the k nearest of its
+//  * ESTABLISH (the first round, the tiles nearest the diagonal): a recipient
+//    keeps its exact k nearest in the tile. A refresh then takes each row's
+//    k-th over these slots: an upper bound of its true k-th distance.
+//  * FILTER (every later round): a recipient keeps the k nearest of its
 //    candidates within its bound. A true neighbour is never above the bound,
 //    so the slots always contain the k nearest.
 #pragma once
@@ -34,18 +33,30 @@
 
 namespace traknn {
 
-// Tile (I, J) = (e, e + h) of establishing tile e: the tiles of each offset
-// h of the geometry, I = 0 .. nbt - h - 1, offset after offset.
-__device__ __forceinline__ bool fused_establish_tile(int64_t e, const FusedGeom& g, int& I,
-                                                     int& J) {
-  for (int u = 0; u < g.nh; ++u) {
-    const int64_t cnt = g.nbt - g.h[u];
-    if (e < cnt) {
-      I = (int)e;
-      J = (int)e + g.h[u];
+// Tile u of a round: the tiles (I, J) with g.blo <= J - I < g.bhi, row by
+// row (row I holds those of its J), so that consecutive tiles share their A
+// panel and neighbouring rows most of their B panels.
+__device__ __forceinline__ bool fused_band_tile(int64_t u, const FusedGeom& g, int& I, int& J) {
+  const int lo = g.blo, hi = g.bhi < g.nbt ? g.bhi : g.nbt;
+  const int w = hi - lo;
+  if (w <= 0) return false;
+  // rows I <= nbt - hi hold all w offsets; later rows nbt - I - lo of them
+  const int64_t full = g.nbt - hi + 1 > 0 ? g.nbt - hi + 1 : 0;
+  if (u < full * w) {
+    I = (int)(u / w);
+    J = I + lo + (int)(u % w);
+    return true;
+  }
+  u -= full * w;
+  for (int i = (int)full; i < g.nbt; ++i) {
+    const int n = g.nbt - i - lo;
+    if (n <= 0) return false;
+    if (u < n) {
+      I = i;
+      J = i + lo + (int)u;
       return true;
     }
-    e -= cnt;
+    u -= n;
   }
   return false;
 }

@@ -224,7 +224,7 @@ __device__ __forceinline__ void interleave_reads() {
   }
 }
 
-// Fused mode (FUSE 1: establishing launch, 2: filtering launch): the tile's
+// Fused mode (FUSE 1: the first round's launch, 2: a later round's): the tile's
 // trajectory stride is fg.B = 256 - (L - 1) rounded down to a multiple of 4,
 // so consecutive tiles overlap by L - 1 fields and hold every term of Eq. 2
 // of their trajectory pairs. After the main loop nothing is stored: the
@@ -253,12 +253,11 @@ __global__ __launch_bounds__(GRAM_THREADS, 1) void gram_kernel(
   __shared__ __attribute__((aligned(16))) char lds[FUSE ? FUSED_LDS : GRAM_LDS];
   float* const nrm = (float*)(lds + GRAM_STAGES * 2 * OPER_BYTES);  // [2][I 256 | J 256]
   int I, J;
-  if constexpr (FUSE == 1) {
-    if (!fused_establish_tile(blockIdx.x, fg, I, J)) return;
-  } else if constexpr (FUSE == 2) {
-    if (!decode_tile(blockIdx.x, fg.nbt, fg.nbt, ntiles, I, J)) return;
-    for (int q = 0; q < fg.nh; ++q)
-      if (J - I == fg.h[q]) return;  // done by the establishing launch
+  if constexpr (FUSE != 0) {
+    // the round's tiles, each XCD a contiguous run of them (as decode_tile)
+    const int64_t per = (ntiles + NUM_XCD - 1) / NUM_XCD;
+    const int64_t lin = (int64_t)(blockIdx.x % NUM_XCD) * per + blockIdx.x / NUM_XCD;
+    if (lin >= ntiles || !fused_band_tile(lin, fg, I, J)) return;
   } else if constexpr (BAND) {
     // the band's tiles that hold entries above the diagonal: J >= J0 + I,
     // the upper triangle of the columns from J0 on, cut to the band's rows
@@ -588,11 +587,9 @@ hipError_t launch_gram_fused(const void* xc, const float* ncs, int64_t T, int64_
                              const double* bound, const FusedSlots& out, hipStream_t s) {
   const int64_t pitch = Dpad * elem_bytes(precision);
   const int nstages = (int)(Dpad / stage_k(precision));
-  const int64_t ntiles = establish ? fused_establish_tiles(g) : (int64_t)g.nbt * (g.nbt + 1) / 2;
+  const int64_t ntiles = fused_band_tiles(g);
   if (ntiles <= 0) return hipSuccess;
-  // establishing tiles in their own order; the rest XCD-aware, as the matrix mode
-  const dim3 grid((unsigned)(establish ? ntiles
-                                       : (ntiles + NUM_XCD - 1) / NUM_XCD * NUM_XCD));
+  const dim3 grid((unsigned)((ntiles + NUM_XCD - 1) / NUM_XCD * NUM_XCD));
   const char* x = (const char*)xc;
 #define TRAKNN_GRAM_FUSED(P, F)                                                           \
   hipLaunchKernelGGL((gram_kernel<P, false, F>), grid, dim3(GRAM_THREADS), 0, s, x, pitch, \

@@ -51,14 +51,17 @@ inline int colstat_chunks(int64_t T) {
 // GRAM_TILE (MFMA Gram) snapshot rows and columns pair B = tile - (L - 1)
 // trajectories (rounded down to a multiple of 4 for the MFMA tiles) with B,
 // so consecutive tiles overlap by L - 1 fields; nbt = ceil(n' / B)
-// block-rows. The establishing launch covers the tiles (I, I + h) of the
-// offsets h[0] = 0 < h[1] < ... (the diagonal band and a few far ones, about
-// one round of the GPU); the filtering launch the rest of the upper triangle.
+// block-rows. The tiles run in rounds of offsets J - I: the first,
+// [0, FUSED_ROUND_END[0]), keeps each recipient's exact k nearest per tile
+// (no bound yet); every later round, [blo, bhi), keeps only the candidates
+// within each row's bound, which a refresh after each round lowers to the
+// k-th of everything seen so far.
 constexpr int FUSED_F64_TILE = 128;
-constexpr int FUSED_MAX_OFFSETS = 8;
+constexpr int FUSED_ROUNDS = 4;
+constexpr int FUSED_ROUND_END[FUSED_ROUNDS - 1] = {2, 8, 32};  // the last round ends at nbt
 struct FusedGeom {
-  int T, np, L, k, B, nbt, nh;
-  int h[FUSED_MAX_OFFSETS];
+  int T, np, L, k, B, nbt;
+  int blo, bhi;  // the launch's offsets J - I: [blo, bhi)
 };
 // Per-row slots of candidate lists: row t meets exactly nbt + 1 tile-sides
 // (the column sides of tiles (I', I_t), I' <= I_t, in slots I'; the row sides
@@ -76,7 +79,7 @@ struct Layout {
   size_t bw_zero, bw_ptr, bw_rev, bw_end;
   size_t mu_part, mu, ncs, xc, S, ST, part_d, part_i;  // forward
   size_t cpart_d, cpart_i;                             // band mode: column windows
-  size_t f_bound, f_cnt, f_sd, f_si;                   // fused mode
+  size_t f_bound, f_cnt, f_sd, f_si, f_rd, f_ri;       // fused mode
   size_t total;
 };
 
@@ -184,22 +187,28 @@ hipError_t launch_backward(const float* X, int64_t ldx, int64_t T, int64_t D,
                            float* g, int64_t ldg, int32_t* zeroed, int32_t* ptr,
                            int32_t* rev, hipStream_t s);
 
-// Fused mode with the MFMA Gram: the establishing (establish = true) or the
-// filtering launch over 256-field tiles of stride g.B.
+// Fused mode with the MFMA Gram: the tiles of offsets [g.blo, g.bhi), over
+// 256-field tiles of stride g.B; establish: each recipient's exact k nearest
+// per tile (no bound), else only candidates within `bound`.
 hipError_t launch_gram_fused(const void* xc, const float* ncs, int64_t T, int64_t Tpad,
                              int64_t Dpad, int precision, const FusedGeom& g, bool establish,
                              const double* bound, const FusedSlots& out, hipStream_t s);
 // fused.hip
-int64_t fused_establish_tiles(const FusedGeom& g);
+int64_t fused_band_tiles(const FusedGeom& g);  // tiles of offsets [g.blo, g.bhi)
 hipError_t launch_fused_f64(const float* X, int64_t ldx, int D, const double* mu,
                             const FusedGeom& g, bool establish, const double* bound,
                             const FusedSlots& out, hipStream_t s);
-// Each row's bound: the k-th distance over its establishing slots.
-hipError_t launch_fused_bound(const FusedGeom& g, const FusedSlots& out, double* bound,
+// After a round of offsets [hlo, hhi): each row's running list (k sorted
+// entries, read only when hlo > 0) merged with the round's slots, and its
+// bound set to the list's k-th (+inf while it holds fewer than k).
+hipError_t launch_slots_refresh(const FusedGeom& g, const FusedSlots& out, double* bound,
+                                double* run_d, int32_t* run_i, int hlo, int hhi,
+                                hipStream_t s);
+// The final lists: the running list (when hlo > 0) merged with the slots of
+// the tiles of offsets hlo and up.
+hipError_t launch_slots_final(const FusedGeom& g, const FusedSlots& out, const double* run_d,
+                              const int32_t* run_i, int hlo, int32_t* idx, double* dist,
                               hipStream_t s);
-// The final lists: the k nearest over all of each row's slots.
-hipError_t launch_fused_select(const FusedGeom& g, const FusedSlots& out, int32_t* idx,
-                               double* dist, hipStream_t s);
 
 // Window stage sizing shared by the planner and the launcher: LDS bytes of a
 // workgroup of W waves for a pass of G lengths whose longest is L, k neighbours.
