@@ -105,10 +105,10 @@ __global__ __launch_bounds__(F64_THREADS) void fused_f64_kernel(
   // The row side (recipients = the tile's rows, slot J + 1) on waves 0-1 and
   // the column side (recipients = its columns, slot I) on waves 2-3.
   const int side = w >> 1;
-  side_topk<TRAKNN_MAX_L>(V, side ? 1 : F64_LD, side ? F64_LD : 1, g.B, g.B,
-                          (int)(side ? j0 : i0), (int)(side ? i0 : j0), side ? -1 : 1,
-                          side ? I : J + 1, g.L, g.np, w & 1, 2, lane,
-                          ESTABLISH ? nullptr : bound, out);
+  side_topk_len<F64_TILE / 64>(g.L, V, side ? 1 : F64_LD, side ? F64_LD : 1, g.B, g.B,
+                               (int)(side ? j0 : i0), (int)(side ? i0 : j0), side ? -1 : 1,
+                               side ? I : J + 1, g.np, w & 1, 2, lane,
+                               ESTABLISH ? nullptr : bound, out);
 }
 
 // One wave per row: the k nearest over some of the row's slots, starting

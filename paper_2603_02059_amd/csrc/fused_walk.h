@@ -74,52 +74,67 @@ __device__ __forceinline__ void slot_write(const FusedSlots& o, int t, int slot,
 
 // The k nearest candidates within `bound` (+inf: all) of recipient s, from
 // direct L-term sums (Eq. 2) over the staged values. The candidates come 64
-// at a time (lane = candidate) and every load of a batch is issued before
-// its sums, so a recipient costs about one LDS round trip per batch. A batch
-// with more than a few candidates within the bound while the list is still
-// empty is sorted; otherwise its candidates within the list's k-th are
-// inserted. Returns how many lanes (from 0) hold entries. The sums run in
-// increasing m, as the matrix mode's windows start them; for FP32 snapshot
-// distances whose exponents span less than about 29 bits every FP64 sum is
-// exact, so both modes give the same D_L.
-template <int MAXL>
+// at a time (lane = candidate); the NB batches of the recipient (Q <= 64 NB)
+// are loaded and summed before their ballots, as many at once as 24 staged
+// values per lane allow, so a recipient costs one or two LDS round trips and
+// chains of L - 1 FP64 adds. A batch with more than
+// a few candidates within the bound while the list is still empty is sorted;
+// otherwise its candidates within the list's k-th are inserted. Returns how
+// many lanes (from 0) hold entries. The sums run in increasing m, as the
+// matrix mode's windows start them; for FP32 snapshot distances whose
+// exponents span less than about 29 bits every FP64 sum is exact, so both
+// modes give the same D_L.
+template <int L, int NB>
 __device__ __forceinline__ int recipient_topk(const float* V, int sp, int sq, int Q, int s,
-                                              int pg, int q0, int sign, int L, int np, int k,
+                                              int pg, int q0, int sign, int np, int k,
                                               double bound, int lane, double& ed, int& ei) {
+  // batches in flight together (a divisor of NB): at most 24 staged values
+  // per lane
+  constexpr int NG = NB * L <= 24 ? NB : (NB % 2 == 0 && NB * L <= 48 ? NB / 2 : 1);
   const int step = sp + sq;
   ed = __builtin_huge_val();
   ei = INT_MAX;
   bool empty = true;
-  for (int c0 = 0; c0 < Q; c0 += 64) {
-    const int q = c0 + lane;
-    const int qg = q0 + q;
-    const int qq = q < Q ? q : 0;  // idle lanes read a valid address
-    const float* v = V + s * sp + qq * sq;
-    float w[MAXL];
 #pragma unroll
-    for (int m = 0; m < MAXL; ++m) w[m] = m < L ? v[m * step] : 0.f;
-    double D = 0.0;
+  for (int b0 = 0; b0 < NB; b0 += NG) {
+    float w[NG][L];
 #pragma unroll
-    for (int m = 0; m < MAXL; ++m)
-      if (m < L) D += (double)w[m];
-    const bool valid = (q < Q) & (qg < np) & (sign * (qg - pg) >= L) & (D <= bound);
-    const uint64_t vm = __ballot(valid);
-    if (!vm) continue;
-    if (empty && __builtin_popcountll(vm) > 8) {
-      double d = valid ? D : __builtin_huge_val();
-      int c = valid ? qg : INT_MAX - 64 + lane;
-      bitonic_sort64(d, c, lane);
-      const bool real = c < INT_MAX - 64;  // the sorted entry is a candidate
-      ed = real ? d : __builtin_huge_val();
-      ei = real ? c : INT_MAX;
-    } else {
-      const double kd = readlane_d(ed, k - 1);
-      const int ki = __builtin_amdgcn_readlane(ei, k - 1);
-      const bool pass = valid && key_less(D, qg, kd, ki);
-      const uint64_t m = __ballot(pass);
-      if (m) insert_reg(m, D, qg, k, ed, ei);
+    for (int b = 0; b < NG; ++b) {
+      const int q = 64 * (b0 + b) + lane;
+      const float* v = V + s * sp + (q < Q ? q : 0) * sq;  // idle lanes: a valid address
+#pragma unroll
+      for (int m = 0; m < L; ++m) w[b][m] = v[m * step];
     }
-    empty = false;
+    double D[NG];
+#pragma unroll
+    for (int b = 0; b < NG; ++b) {
+      D[b] = (double)w[b][0];
+#pragma unroll
+      for (int m = 1; m < L; ++m) D[b] += (double)w[b][m];
+    }
+#pragma unroll
+    for (int b = 0; b < NG; ++b) {
+      const int q = 64 * (b0 + b) + lane;
+      const int qg = q0 + q;
+      const bool valid = (q < Q) & (qg < np) & (sign * (qg - pg) >= L) & (D[b] <= bound);
+      const uint64_t vm = __ballot(valid);
+      if (!vm) continue;
+      if (empty && __builtin_popcountll(vm) > 8) {
+        double d = valid ? D[b] : __builtin_huge_val();
+        int c = valid ? qg : INT_MAX - 64 + lane;
+        bitonic_sort64(d, c, lane);
+        const bool real = c < INT_MAX - 64;  // the sorted entry is a candidate
+        ed = real ? d : __builtin_huge_val();
+        ei = real ? c : INT_MAX;
+      } else {
+        const double kd = readlane_d(ed, k - 1);
+        const int ki = __builtin_amdgcn_readlane(ei, k - 1);
+        const bool pass = valid && key_less(D[b], qg, kd, ki);
+        const uint64_t m = __ballot(pass);
+        if (m) insert_reg(m, D[b], qg, k, ed, ei);
+      }
+      empty = false;
+    }
   }
   return __builtin_popcountll(__ballot(lane < k && ei != INT_MAX));
 }
@@ -128,12 +143,11 @@ __device__ __forceinline__ int recipient_topk(const float* V, int sp, int sq, in
 // 0 .. P - 1 and writes their slots. ESTABLISH (bound == nullptr): each
 // recipient's exact k nearest in the tile. FILTER: its k nearest within its
 // row's bound (the bounds of the wave's recipients are fetched first, one per
-// lane, and read from registers).
-template <int MAXL>
+// lane, and read from registers). Q <= 64 NB candidates per recipient.
+template <int L, int NB>
 __device__ __forceinline__ void side_topk(const float* V, int sp, int sq, int Q, int P, int p0,
-                                          int q0, int sign, int slot, int L, int np, int wave,
-                                          int nw, int lane, const double* bound,
-                                          const FusedSlots& out) {
+                                          int q0, int sign, int slot, int np, int wave, int nw,
+                                          int lane, const double* bound, const FusedSlots& out) {
   double mybound = __builtin_huge_val();
   if (bound) {
     const int pl = p0 + wave + lane * nw;  // lane u: the wave's u-th recipient
@@ -146,9 +160,25 @@ __device__ __forceinline__ void side_topk(const float* V, int sp, int sq, int Q,
     double ed;
     int ei;
     const double b = bound ? readlane_d(mybound, u) : __builtin_huge_val();
-    const int n = recipient_topk<MAXL>(V, sp, sq, Q, s, pg, q0, sign, L, np, out.k, b, lane,
-                                       ed, ei);
+    const int n = recipient_topk<L, NB>(V, sp, sq, Q, s, pg, q0, sign, np, out.k, b, lane,
+                                        ed, ei);
     slot_write(out, pg, slot, n, ed, ei, lane);
+  }
+}
+
+// side_topk for the run-time length L (1 .. TRAKNN_MAX_L): each length has
+// its own unrolled sums.
+template <int NB, int LC = 1>
+__device__ __forceinline__ void side_topk_len(int L, const float* V, int sp, int sq, int Q, int P,
+                                              int p0, int q0, int sign, int slot, int np,
+                                              int wave, int nw, int lane, const double* bound,
+                                              const FusedSlots& out) {
+  if constexpr (LC <= TRAKNN_MAX_L) {
+    if (L == LC)
+      side_topk<LC, NB>(V, sp, sq, Q, P, p0, q0, sign, slot, np, wave, nw, lane, bound, out);
+    else
+      side_topk_len<NB, LC + 1>(L, V, sp, sq, Q, P, p0, q0, sign, slot, np, wave, nw, lane,
+                                bound, out);
   }
 }
 

@@ -433,9 +433,9 @@ __global__ __launch_bounds__(GRAM_THREADS, 1) void gram_kernel(
       // row parts: recipients are the tile's rows (slot J + 1); column parts:
       // its columns (slot I)
       const int p0 = (cols ? J : I) * fg.B + off, q0 = (cols ? I : J) * fg.B;
-      side_topk<TRAKNN_MAX_L>(V, FPITCH, 1, fg.B, hs, p0, q0, cols ? -1 : 1, cols ? I : J + 1,
-                              fg.L, fg.np, w, GRAM_THREADS / 64, lane,
-                              FUSE == 1 ? nullptr : fbound, fout);
+      side_topk_len<TILE / 64>(fg.L, V, FPITCH, 1, fg.B, hs, p0, q0, cols ? -1 : 1,
+                               cols ? I : J + 1, fg.np, w, GRAM_THREADS / 64, lane,
+                               FUSE == 1 ? nullptr : fbound, fout);
       __syncthreads();
     }
     return;
