@@ -118,9 +118,10 @@ __global__ __launch_bounds__(256) void rev_sort_kernel(const int32_t* __restrict
 // threads holds GB_VEC groups of 4 consecutive columns, loaded and stored as
 // 16-byte vectors (strided rows fall back to scalar stores of the output).
 // Rows that no term touches are written as zeros and nothing else; touched
-// rows gather their terms with every term's GB_VEC source vectors in flight
-// at once, in FP64, rounded once to FP32.
-constexpr int GB_VEC = 4;
+// rows gather their terms in FP64, GB_BATCH terms' source vectors in flight at
+// once, rounded once to FP32.
+constexpr int GB_VEC = 1;
+constexpr int GB_BATCH = 4;  // terms whose source vectors are loaded together
 constexpr int GB_COLS = 256 * 4 * GB_VEC;
 
 template <bool VEC_OUT>
@@ -166,17 +167,37 @@ __global__ __launch_bounds__(256) void grad_rows_kernel(
     for (int e = 0; e < 4; ++e) acc[v][e] = 0.0;
   }
   const double invk = 1.0 / (double)k;
-  auto term = [&](int64_t b, double c) __attribute__((always_inline)) {
-    float4 xb[GB_VEC];
+  // Terms go in batches of GB_BATCH, every source vector of a batch loaded
+  // before any is used, so a row with many terms waits for one memory round
+  // trip per batch instead of one per term. Unused entries of a batch read the
+  // row itself with weight 0 (an exact zero contribution).
+  int64_t tb[GB_BATCH];
+  double tc[GB_BATCH];
+  int nt = 0;
+  auto flush = [&]() __attribute__((always_inline)) {
+    float4 xb[GB_BATCH][GB_VEC];
 #pragma unroll
-    for (int v = 0; v < GB_VEC; ++v) xb[v] = load(b, v);
+    for (int u = 0; u < GB_BATCH; ++u)
 #pragma unroll
-    for (int v = 0; v < GB_VEC; ++v) {
-      acc[v][0] += c * (xa[v][0] - (double)xb[v].x);
-      acc[v][1] += c * (xa[v][1] - (double)xb[v].y);
-      acc[v][2] += c * (xa[v][2] - (double)xb[v].z);
-      acc[v][3] += c * (xa[v][3] - (double)xb[v].w);
+      for (int v = 0; v < GB_VEC; ++v) xb[u][v] = load(u < nt ? tb[u] : a, v);
+#pragma unroll
+    for (int u = 0; u < GB_BATCH; ++u) {
+      const double c = u < nt ? tc[u] : 0.0;
+#pragma unroll
+      for (int v = 0; v < GB_VEC; ++v) {
+        acc[v][0] += c * (xa[v][0] - (double)xb[u][v].x);
+        acc[v][1] += c * (xa[v][1] - (double)xb[u][v].y);
+        acc[v][2] += c * (xa[v][2] - (double)xb[u][v].z);
+        acc[v][3] += c * (xa[v][3] - (double)xb[u][v].w);
+      }
     }
+    nt = 0;
+  };
+  auto term = [&](int64_t b, double c) __attribute__((always_inline)) {
+#pragma unroll
+    for (int u = 0; u < GB_BATCH; ++u)
+      if (u == nt) tb[u] = b, tc[u] = c;
+    if (++nt == GB_BATCH) flush();
   };
   // W_ab: a = t + m, b = j + m for j in N_t
   for (int m = 0; m < L; ++m) {
@@ -200,6 +221,7 @@ __global__ __launch_bounds__(256) void grad_rows_kernel(
       term(t + m, w[t] * invk);
     }
   }
+  if (nt) flush();
 #pragma unroll
   for (int v = 0; v < GB_VEC; ++v)
     store(cbase + 1024 * v, make_float4((float)(2.0 * acc[v][0]), (float)(2.0 * acc[v][1]),

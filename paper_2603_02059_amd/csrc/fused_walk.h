@@ -72,22 +72,38 @@ __device__ __forceinline__ void slot_write(const FusedSlots& o, int t, int slot,
   }
 }
 
+// An FP32 bound that no FP32 sum of L <= 16 non-negative FP32 terms exceeds
+// when the FP64 sum of the same terms is at most `bound`: recursive FP32
+// summation errs by at most (L - 1) 2^-24 / (1 - (L - 1) 2^-24) < 2^-20 of the
+// exact sum, and the FP64 sum by far less, so bound (1 + 2^-20) rounded up to
+// FP32 is safe (+inf stays +inf, a negative bound stays negative).
+__device__ __forceinline__ float prefilter_bound(double bound) {
+  const double b = bound > 0.0 ? bound * (1.0 + 0x1p-20) : bound;
+  float f = (float)b;
+  // below b (only if b > 0): the next float up, by its bit pattern
+  if ((double)f < b) f = __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, f) + 1u);
+  return f;
+}
+
 // The k nearest candidates within `bound` (+inf: all) of recipient s, from
 // direct L-term sums (Eq. 2) over the staged values. The candidates come 64
 // at a time (lane = candidate); the NB batches of the recipient (Q <= 64 NB)
-// are loaded and summed before their ballots, as many at once as 24 staged
-// values per lane allow, so a recipient costs one or two LDS round trips and
-// chains of L - 1 FP64 adds. A batch with more than
-// a few candidates within the bound while the list is still empty is sorted;
-// otherwise its candidates within the list's k-th are inserted. Returns how
-// many lanes (from 0) hold entries. The sums run in increasing m, as the
-// matrix mode's windows start them; for FP32 snapshot distances whose
-// exponents span less than about 29 bits every FP64 sum is exact, so both
-// modes give the same D_L.
-template <int L, int NB>
+// are loaded before their ballots, as many at once as 24 staged values per
+// lane allow, so a recipient costs one or two LDS round trips. With a finite
+// bound (FILTER) each batch is first tested on its FP32 sums against bound32
+// (prefilter_bound): a candidate whose FP64 sum is within the bound always
+// passes, and only batches where some candidate passes form the FP64 sums,
+// which decide. A batch with more than a few candidates within the bound
+// while the list is still empty is sorted; otherwise its candidates within
+// the list's k-th are inserted. Returns how many lanes (from 0) hold entries.
+// The FP64 sums run in increasing m, as the matrix mode's windows start them;
+// for FP32 snapshot distances whose exponents span less than about 29 bits
+// every FP64 sum is exact, so both modes give the same D_L.
+template <int L, int NB, bool FILTER>
 __device__ __forceinline__ int recipient_topk(const float* V, int sp, int sq, int Q, int s,
                                               int pg, int q0, int sign, int np, int k,
-                                              double bound, int lane, double& ed, int& ei) {
+                                              double bound, float bound32, int lane,
+                                              double& ed, int& ei) {
   // batches in flight together (a divisor of NB): at most 24 staged values
   // per lane
   constexpr int NG = NB * L <= 24 ? NB : (NB % 2 == 0 && NB * L <= 48 ? NB / 2 : 1);
@@ -105,22 +121,31 @@ __device__ __forceinline__ int recipient_topk(const float* V, int sp, int sq, in
 #pragma unroll
       for (int m = 0; m < L; ++m) w[b][m] = v[m * step];
     }
-    double D[NG];
-#pragma unroll
-    for (int b = 0; b < NG; ++b) {
-      D[b] = (double)w[b][0];
-#pragma unroll
-      for (int m = 1; m < L; ++m) D[b] += (double)w[b][m];
-    }
+    bool cand[NG];  // in range, outside the exclusion zone (and, FILTER, FP32 sum within)
 #pragma unroll
     for (int b = 0; b < NG; ++b) {
       const int q = 64 * (b0 + b) + lane;
       const int qg = q0 + q;
-      const bool valid = (q < Q) & (qg < np) & (sign * (qg - pg) >= L) & (D[b] <= bound);
+      cand[b] = (q < Q) & (qg < np) & (sign * (qg - pg) >= L);
+      if constexpr (FILTER) {
+        float s32 = w[b][0];
+#pragma unroll
+        for (int m = 1; m < L; ++m) s32 += w[b][m];
+        cand[b] = cand[b] & (s32 <= bound32);
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < NG; ++b) {
+      if (!__ballot(cand[b])) continue;
+      const int qg = q0 + 64 * (b0 + b) + lane;
+      double D = (double)w[b][0];
+#pragma unroll
+      for (int m = 1; m < L; ++m) D += (double)w[b][m];
+      const bool valid = cand[b] & (D <= bound);
       const uint64_t vm = __ballot(valid);
       if (!vm) continue;
       if (empty && __builtin_popcountll(vm) > 8) {
-        double d = valid ? D[b] : __builtin_huge_val();
+        double d = valid ? D : __builtin_huge_val();
         int c = valid ? qg : INT_MAX - 64 + lane;
         bitonic_sort64(d, c, lane);
         const bool real = c < INT_MAX - 64;  // the sorted entry is a candidate
@@ -129,9 +154,9 @@ __device__ __forceinline__ int recipient_topk(const float* V, int sp, int sq, in
       } else {
         const double kd = readlane_d(ed, k - 1);
         const int ki = __builtin_amdgcn_readlane(ei, k - 1);
-        const bool pass = valid && key_less(D[b], qg, kd, ki);
+        const bool pass = valid && key_less(D, qg, kd, ki);
         const uint64_t m = __ballot(pass);
-        if (m) insert_reg(m, D[b], qg, k, ed, ei);
+        if (m) insert_reg(m, D, qg, k, ed, ei);
       }
       empty = false;
     }
@@ -148,21 +173,34 @@ template <int L, int NB>
 __device__ __forceinline__ void side_topk(const float* V, int sp, int sq, int Q, int P, int p0,
                                           int q0, int sign, int slot, int np, int wave, int nw,
                                           int lane, const double* bound, const FusedSlots& out) {
-  double mybound = __builtin_huge_val();
   if (bound) {
     const int pl = p0 + wave + lane * nw;  // lane u: the wave's u-th recipient
-    mybound = (wave + lane * nw < P && pl < np) ? bound[pl] : -1.0;
-  }
-  int u = 0;
-  for (int s = wave; s < P; s += nw, ++u) {
-    const int pg = p0 + s;
-    if (pg >= np) continue;
-    double ed;
-    int ei;
-    const double b = bound ? readlane_d(mybound, u) : __builtin_huge_val();
-    const int n = recipient_topk<L, NB>(V, sp, sq, Q, s, pg, q0, sign, np, out.k, b, lane,
-                                        ed, ei);
-    slot_write(out, pg, slot, n, ed, ei, lane);
+    const double mybound = (wave + lane * nw < P && pl < np) ? bound[pl] : -1.0;
+    const float mybound32 = prefilter_bound(mybound);
+    int u = 0;
+    for (int s = wave; s < P; s += nw, ++u) {
+      const int pg = p0 + s;
+      if (pg >= np) continue;
+      double ed;
+      int ei;
+      const double b = readlane_d(mybound, u);
+      const float b32 = __builtin_bit_cast(
+          float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, mybound32), u));
+      const int n = recipient_topk<L, NB, true>(V, sp, sq, Q, s, pg, q0, sign, np, out.k, b,
+                                                b32, lane, ed, ei);
+      slot_write(out, pg, slot, n, ed, ei, lane);
+    }
+  } else {
+    for (int s = wave; s < P; s += nw) {
+      const int pg = p0 + s;
+      if (pg >= np) continue;
+      double ed;
+      int ei;
+      const int n = recipient_topk<L, NB, false>(V, sp, sq, Q, s, pg, q0, sign, np, out.k,
+                                                 __builtin_huge_val(), __builtin_huge_valf(),
+                                                 lane, ed, ei);
+      slot_write(out, pg, slot, n, ed, ei, lane);
+    }
   }
 }
 
