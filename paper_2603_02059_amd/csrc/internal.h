@@ -213,14 +213,14 @@ hipError_t launch_slots_final(const FusedGeom& g, const FusedSlots& out, const d
 // Window stage sizing shared by the planner and the launcher: LDS bytes of a
 // workgroup of W waves for a pass of G lengths whose longest is L, k neighbours.
 size_t window1_lds_bytes(int L, int G, int k, int W);
-// Lengths a multi-length sweep handles per pass over S (1 or 2; compile-time
+// Lengths a multi-length sweep handles per pass over S (1 to 5; compile-time
 // tuning knob). Each pass reads S once for all of its lengths.
 #ifndef TRAKNN_WIN_LENGTHS_PER_PASS
 #define TRAKNN_WIN_LENGTHS_PER_PASS 2
 #endif
 constexpr int WINDOW_LENGTHS_PER_PASS = TRAKNN_WIN_LENGTHS_PER_PASS;
-static_assert(WINDOW_LENGTHS_PER_PASS == 1 || WINDOW_LENGTHS_PER_PASS == 2,
-              "one or two lengths per window pass");
+static_assert(WINDOW_LENGTHS_PER_PASS >= 1 && WINDOW_LENGTHS_PER_PASS <= 5,
+              "one to five lengths per window pass");
 // Rows per window block (a multiple of the 8-step group; compile-time tuning
 // knob, 8 measured best on the full workload).
 #ifndef TRAKNN_WINDOW1_ROWS

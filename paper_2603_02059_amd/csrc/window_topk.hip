@@ -466,7 +466,8 @@ __global__ __launch_bounds__(256) void local_dim_kernel(
 }  // namespace
 
 // Launchers of every compiled (L, G): kWin1[L - 1] for L = 1..TRAKNN_MAX_L on
-// its own, kWin2[L - 1] for the pair (L, L + 1).
+// its own, kWinG[L - 1] for the lengths L .. L + WINDOW_LENGTHS_PER_PASS - 1
+// of a sweep's pass.
 using WinLaunch = hipError_t (*)(const float*, int64_t, int, int, int, int, int, int, int, int,
                                  int, int, int, int, int, int64_t, int64_t, double*, int32_t*,
                                  hipStream_t);
@@ -475,7 +476,8 @@ constexpr std::array<WinLaunch, sizeof...(Ls)> win_table(std::integer_sequence<i
   return {&launch_win1<Ls + 1, G>...};
 }
 constexpr auto kWin1 = win_table<1>(std::make_integer_sequence<int, TRAKNN_MAX_L>{});
-constexpr auto kWin2 = win_table<2>(std::make_integer_sequence<int, TRAKNN_MAX_L - 1>{});
+constexpr auto kWinG = win_table<WINDOW_LENGTHS_PER_PASS>(
+    std::make_integer_sequence<int, TRAKNN_MAX_L - WINDOW_LENGTHS_PER_PASS + 1>{});
 
 size_t window1_lds_bytes(int L, int G, int k, int W) {
   return (size_t)G * W1_ROWS * sizeof(unsigned long long) +
@@ -509,7 +511,7 @@ hipError_t launch_window_band(const float* S, int64_t ldS, int64_t T, int L_min,
     const int64_t hi = t0 + nt < T - L + 1 ? t0 + nt : T - L + 1;
     if (hi > t0) {
       if (L < 1 || L + G - 1 > TRAKNN_MAX_L) return hipErrorInvalidValue;
-      const WinLaunch f = G == 2 ? kWin2[L - 1] : kWin1[L - 1];
+      const WinLaunch f = G > 1 ? kWinG[L - 1] : kWin1[L - 1];
       const hipError_t e =
           f(S, ldS, (int)T, (int)r.s0, (int)r.s_end, (int)r.col0, (int)r.c_lo, (int)r.c_hi,
             (int)r.v_end, (int)r.dmin, (int)r.dmax, (int)t0, (int)(t0 + nt), k, splits,
