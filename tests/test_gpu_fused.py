@@ -132,7 +132,8 @@ def test_fused_f64_small_d_full_length(shape, k):
     (613, 77, 6, 3, "fp16"),
     (520, 300, 16, 64, "bf16x3"),   # longest length: 240-field tile stride
     (1100, 64, 1, 10, "bf16x3"),    # L = 1: 256-field stride, several offsets
-    (2600, 40, 2, 4, "fp32"),       # ten block-rows, four establishing offsets
+    (2600, 40, 2, 4, "fp32"),       # eleven block-rows, three rounds of offsets
+    (1800, 50, 9, 6, "bf16x3"),     # lengths 7-12: two candidate batches in flight
 ])
 def test_fused_mfma_equals_matrix(T, D, L, k, prec):
     """The MFMA-fused mode forms each distance from the same operands in the
