@@ -47,6 +47,8 @@ __global__ __launch_bounds__(F64_THREADS) void fused_f64_kernel(
     FusedGeom g, const double* __restrict__ bound, FusedSlots out) {
   __shared__ __attribute__((aligned(16))) char un[F64_UNION_BYTES];
   __shared__ double nrm[2][F64_TILE];  // squared norms of the A and B rows
+  __shared__ double est_d[F64_THREADS / 64][64];  // each wave's first-round scratch
+  __shared__ int est_i[F64_THREADS / 64][64];
   int I, J;
   if (!fused_band_tile(blockIdx.x, g, I, J)) return;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -105,10 +107,10 @@ __global__ __launch_bounds__(F64_THREADS) void fused_f64_kernel(
   // The row side (recipients = the tile's rows, slot J + 1) on waves 0-1 and
   // the column side (recipients = its columns, slot I) on waves 2-3.
   const int side = w >> 1;
-  side_topk_len<F64_TILE / 64>(g.L, V, side ? 1 : F64_LD, side ? F64_LD : 1, g.B, g.B,
+  side_topk_len<F64_TILE / 64, ESTABLISH>(g.L, V, side ? 1 : F64_LD, side ? F64_LD : 1, g.B, g.B,
                                (int)(side ? j0 : i0), (int)(side ? i0 : j0), side ? -1 : 1,
                                side ? I : J + 1, g.np, w & 1, 2, lane,
-                               ESTABLISH ? nullptr : bound, out);
+                               bound, out, EstScratch{est_d[w], est_i[w]});
 }
 
 // One wave per row: the k nearest over some of the row's slots, starting

@@ -164,16 +164,131 @@ __device__ __forceinline__ int recipient_topk(const float* V, int sp, int sq, in
   return __builtin_popcountll(__ballot(lane < k && ei != INT_MAX));
 }
 
+// Per-wave LDS scratch of the first round: up to 64 compacted candidates.
+struct EstScratch {
+  double* d;  // [64]
+  int* i;     // [64]
+};
+constexpr int EST_SCRATCH_BYTES = 64 * (sizeof(double) + sizeof(int));
+
+// The k-th smallest of the wave's 64 keys (bitonic network of lane exchanges
+// on the keys alone; keys are non-negative or +inf).
+__device__ __forceinline__ float kth_smallest64(float key, int lane, int k) {
+#pragma unroll
+  for (int size = 2; size <= 64; size <<= 1)
+#pragma unroll
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      const float p = __shfl_xor(key, stride, 64);
+      const bool keep_min = ((lane & stride) == 0) == ((lane & size) == 0);
+      key = keep_min ? __builtin_fminf(key, p) : __builtin_fmaxf(key, p);
+    }
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, key), k - 1));
+}
+
+// First round (no bound yet): recipient s's exact k nearest in the tile,
+// possibly unsorted. Each lane takes the smallest FP32 window sum over its
+// candidates; the k-th smallest of these 64 minima, tau, belongs to k
+// distinct candidates, whose FP64 sums are at most tau (1 + 2^-19) (the FP32
+// sums err by less than 2^-20, the FP64 ones by far less). That value bounds
+// the tile's k-th distance, so the candidates within it -- at least k -- hold
+// the k nearest. They are compacted into the wave's scratch and, if there are
+// more than k, sorted. Fewer than k lanes with a candidate, or more than 64
+// candidates within the bound, fall back to recipient_topk with no bound.
+template <int L, int NB>
+__device__ __forceinline__ int recipient_establish(const float* V, int sp, int sq, int Q, int s,
+                                                   int pg, int q0, int sign, int np, int k,
+                                                   int lane, const EstScratch& sc, double& ed,
+                                                   int& ei) {
+  // batches in flight together: at most 12 staged values per lane, so that
+  // the first round's kernels keep their accumulators in registers
+  constexpr int NG = NB * L <= 12 ? NB : (NB % 2 == 0 && NB * L <= 24 ? NB / 2 : 1);
+  const int step = sp + sq;
+  const float* vrow = V + s * sp;
+  auto load = [&](int b0, float (&w)[NG][L]) __attribute__((always_inline)) {
+#pragma unroll
+    for (int b = 0; b < NG; ++b) {
+      const int q = 64 * (b0 + b) + lane;
+      const float* v = vrow + (q < Q ? q : 0) * sq;  // idle lanes: a valid address
+#pragma unroll
+      for (int m = 0; m < L; ++m) w[b][m] = v[m * step];
+    }
+  };
+  auto is_cand = [&](int b) __attribute__((always_inline)) {
+    const int q = 64 * b + lane;
+    const int qg = q0 + q;
+    return (q < Q) & (qg < np) & (sign * (qg - pg) >= L);
+  };
+  float mn = __builtin_huge_valf();
+#pragma unroll
+  for (int b0 = 0; b0 < NB; b0 += NG) {
+    float w[NG][L];
+    load(b0, w);
+#pragma unroll
+    for (int b = 0; b < NG; ++b) {
+      float s32 = w[b][0];
+#pragma unroll
+      for (int m = 1; m < L; ++m) s32 += w[b][m];
+      if (is_cand(b0 + b)) mn = __builtin_fminf(mn, s32);
+    }
+  }
+  const float tau = kth_smallest64(mn, lane, k);
+  bool fallback = tau == __builtin_huge_valf();  // fewer than k lanes hold a candidate
+  const double b64 = (double)tau * (1.0 + 0x1p-19);
+  const float b32 = prefilter_bound(b64);
+  int total = 0;
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll
+  for (int b0 = 0; b0 < NB && !fallback; b0 += NG) {
+    float w[NG][L];
+    load(b0, w);
+#pragma unroll
+    for (int b = 0; b < NG; ++b) {
+      float s32 = w[b][0];
+#pragma unroll
+      for (int m = 1; m < L; ++m) s32 += w[b][m];
+      bool c = is_cand(b0 + b) & (s32 <= b32);
+      if (!__ballot(c)) continue;
+      double D = (double)w[b][0];
+#pragma unroll
+      for (int m = 1; m < L; ++m) D += (double)w[b][m];
+      c = c & (D <= b64);
+      const uint64_t mk = __ballot(c);
+      const int pos = total + (int)__builtin_amdgcn_mbcnt_hi(
+                                  (uint32_t)(mk >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0));
+      if (c && pos < 64) {
+        sc.d[pos] = D;
+        sc.i[pos] = q0 + 64 * (b0 + b) + lane;
+      }
+      total += __builtin_popcountll(mk);
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+  if (fallback || total > 64)
+    return recipient_topk<L, NB, false>(V, sp, sq, Q, s, pg, q0, sign, np, k,
+                                        __builtin_huge_val(), __builtin_huge_valf(), lane, ed,
+                                        ei);
+  double d = lane < total ? sc.d[lane] : __builtin_huge_val();
+  int c = lane < total ? sc.i[lane] : INT_MAX - 64 + lane;
+  __builtin_amdgcn_wave_barrier();  // the scratch is read before the next recipient writes it
+  if (total > k) bitonic_sort64(d, c, lane);
+  const bool real = lane < (total < k ? total : k);
+  ed = real ? d : __builtin_huge_val();
+  ei = real ? c : INT_MAX;
+  return total < k ? total : k;
+}
+
 // One side of a staged part: wave w of nw keeps recipients w, w + nw, ... of
-// 0 .. P - 1 and writes their slots. ESTABLISH (bound == nullptr): each
-// recipient's exact k nearest in the tile. FILTER: its k nearest within its
+// 0 .. P - 1 and writes their slots. ESTABLISH (the first round): each
+// recipient's exact k nearest in the tile (recipient_establish, using the
+// wave's scratch sc). Otherwise (FILTER): its k nearest within its
 // row's bound (the bounds of the wave's recipients are fetched first, one per
 // lane, and read from registers). Q <= 64 NB candidates per recipient.
-template <int L, int NB>
+template <int L, int NB, bool ESTABLISH>
 __device__ __forceinline__ void side_topk(const float* V, int sp, int sq, int Q, int P, int p0,
                                           int q0, int sign, int slot, int np, int wave, int nw,
-                                          int lane, const double* bound, const FusedSlots& out) {
-  if (bound) {
+                                          int lane, const double* bound, const FusedSlots& out,
+                                          const EstScratch& sc) {
+  if constexpr (!ESTABLISH) {
     const int pl = p0 + wave + lane * nw;  // lane u: the wave's u-th recipient
     const double mybound = (wave + lane * nw < P && pl < np) ? bound[pl] : -1.0;
     const float mybound32 = prefilter_bound(mybound);
@@ -196,9 +311,8 @@ __device__ __forceinline__ void side_topk(const float* V, int sp, int sq, int Q,
       if (pg >= np) continue;
       double ed;
       int ei;
-      const int n = recipient_topk<L, NB, false>(V, sp, sq, Q, s, pg, q0, sign, np, out.k,
-                                                 __builtin_huge_val(), __builtin_huge_valf(),
-                                                 lane, ed, ei);
+      const int n = recipient_establish<L, NB>(V, sp, sq, Q, s, pg, q0, sign, np, out.k, lane,
+                                               sc, ed, ei);
       slot_write(out, pg, slot, n, ed, ei, lane);
     }
   }
@@ -206,17 +320,18 @@ __device__ __forceinline__ void side_topk(const float* V, int sp, int sq, int Q,
 
 // side_topk for the run-time length L (1 .. TRAKNN_MAX_L): each length has
 // its own unrolled sums.
-template <int NB, int LC = 1>
+template <int NB, bool ESTABLISH, int LC = 1>
 __device__ __forceinline__ void side_topk_len(int L, const float* V, int sp, int sq, int Q, int P,
                                               int p0, int q0, int sign, int slot, int np,
                                               int wave, int nw, int lane, const double* bound,
-                                              const FusedSlots& out) {
+                                              const FusedSlots& out, const EstScratch& sc) {
   if constexpr (LC <= TRAKNN_MAX_L) {
     if (L == LC)
-      side_topk<LC, NB>(V, sp, sq, Q, P, p0, q0, sign, slot, np, wave, nw, lane, bound, out);
+      side_topk<LC, NB, ESTABLISH>(V, sp, sq, Q, P, p0, q0, sign, slot, np, wave, nw, lane,
+                                   bound, out, sc);
     else
-      side_topk_len<NB, LC + 1>(L, V, sp, sq, Q, P, p0, q0, sign, slot, np, wave, nw, lane,
-                                bound, out);
+      side_topk_len<NB, ESTABLISH, LC + 1>(L, V, sp, sq, Q, P, p0, q0, sign, slot, np, wave, nw,
+                                           lane, bound, out, sc);
   }
 }
 

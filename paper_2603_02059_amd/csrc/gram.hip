@@ -240,7 +240,10 @@ constexpr int FPITCH = TILE + 1;  // floats per staged row (odd: transposed read
 constexpr int FUSED_MAX_STAGED = (GRAM_TILE - 16) / 2 + 15;  // rows of a part, L <= 16
 constexpr int FUSED_VAL_BYTES = FUSED_MAX_STAGED * FPITCH * 4;
 constexpr int GRAM_LDS = GRAM_STAGES * 2 * OPER_BYTES + NORM_LDS;
-constexpr int FUSED_LDS = FUSED_VAL_BYTES > GRAM_LDS ? FUSED_VAL_BYTES : GRAM_LDS;
+// the staged part, then each wave's first-round scratch
+constexpr int FUSED_EST_OFFSET = (FUSED_VAL_BYTES + 15) / 16 * 16;
+constexpr int FUSED_EST_BYTES = FUSED_EST_OFFSET + (GRAM_THREADS / 64) * EST_SCRATCH_BYTES;
+constexpr int FUSED_LDS = FUSED_EST_BYTES > GRAM_LDS ? FUSED_EST_BYTES : GRAM_LDS;
 static_assert(FUSED_LDS <= 160 * 1024, "a fused part must fit in the LDS of a CU");
 
 template <int PREC, bool BAND, int FUSE = 0>
@@ -433,9 +436,11 @@ __global__ __launch_bounds__(GRAM_THREADS, 1) void gram_kernel(
       // row parts: recipients are the tile's rows (slot J + 1); column parts:
       // its columns (slot I)
       const int p0 = (cols ? J : I) * fg.B + off, q0 = (cols ? I : J) * fg.B;
-      side_topk_len<TILE / 64>(fg.L, V, FPITCH, 1, fg.B, hs, p0, q0, cols ? -1 : 1,
-                               cols ? I : J + 1, fg.np, w, GRAM_THREADS / 64, lane,
-                               FUSE == 1 ? nullptr : fbound, fout);
+      char* est = lds + FUSED_EST_OFFSET + w * EST_SCRATCH_BYTES;
+      const EstScratch sc{(double*)est, (int*)(est + 64 * sizeof(double))};
+      side_topk_len<TILE / 64, FUSE == 1>(fg.L, V, FPITCH, 1, fg.B, hs, p0, q0, cols ? -1 : 1,
+                                          cols ? I : J + 1, fg.np, w, GRAM_THREADS / 64, lane,
+                                          fbound, fout, sc);
       __syncthreads();
     }
     return;

@@ -58,6 +58,8 @@ def _all_rows(Xn, L, k, got, label):
     (700, 1000, 1, 1),     # L = 1, k = 1: snapshot matrix profile
     (520, 300, 16, 64),    # longest length, largest k
     (1100, 13, 5, 10),     # several establishing offsets, far tiles
+    (100, 40, 5, 7),       # one block of trajectories: the first round only
+    (129, 40, 1, 8),       # a second block holding one trajectory
 ])
 def test_fused_f64_small(T, D, L, k):
     _say(f"[gpu-fused] fp64 T={T} D={D} L={L} k={k}")
@@ -134,6 +136,8 @@ def test_fused_f64_small_d_full_length(shape, k):
     (1100, 64, 1, 10, "bf16x3"),    # L = 1: 256-field stride, several offsets
     (2600, 40, 2, 4, "fp32"),       # eleven block-rows, three rounds of offsets
     (1800, 50, 9, 6, "bf16x3"),     # lengths 7-12: two candidate batches in flight
+    (200, 64, 5, 7, "bf16x3"),      # one block of trajectories: the first round only
+    (257, 64, 2, 5, "fp32"),        # a second block of four trajectories
 ])
 def test_fused_mfma_equals_matrix(T, D, L, k, prec):
     """The MFMA-fused mode forms each distance from the same operands in the
