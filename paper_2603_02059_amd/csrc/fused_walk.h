@@ -85,6 +85,13 @@ __device__ __forceinline__ float prefilter_bound(double bound) {
   return f;
 }
 
+// Per-wave LDS scratch of a recipient's candidates: up to 64 compacted entries.
+struct EstScratch {
+  double* d;  // [64]
+  int* i;     // [64]
+};
+constexpr int EST_SCRATCH_BYTES = 64 * (sizeof(double) + sizeof(int));
+
 // The k nearest candidates within `bound` (+inf: all) of recipient s, from
 // direct L-term sums (Eq. 2) over the staged values. The candidates come 64
 // at a time (lane = candidate); the NB batches of the recipient (Q <= 64 NB)
@@ -93,24 +100,29 @@ __device__ __forceinline__ float prefilter_bound(double bound) {
 // bound (FILTER) each batch is first tested on its FP32 sums against bound32
 // (prefilter_bound): a candidate whose FP64 sum is within the bound always
 // passes, and only batches where some candidate passes form the FP64 sums,
-// which decide. A batch with more than a few candidates within the bound
-// while the list is still empty is sorted; otherwise its candidates within
-// the list's k-th are inserted. Returns how many lanes (from 0) hold entries.
-// The FP64 sums run in increasing m, as the matrix mode's windows start them;
-// for FP32 snapshot distances whose exponents span less than about 29 bits
-// every FP64 sum is exact, so both modes give the same D_L.
+// which decide. Candidates within the bound are compacted into the wave's
+// scratch; while there are at most 64 of them nothing is compared, and at
+// the end more than k are sorted (the k smallest kept) and at most k are
+// kept as they are, unsorted. A batch that would take the scratch past 64
+// entries turns it into a sorted list in registers, into which that batch
+// and the later ones are inserted. Returns how many lanes (from 0) hold
+// entries. The FP64 sums run in increasing m, as the matrix mode's windows
+// start them; for FP32 snapshot distances whose exponents span less than
+// about 29 bits every FP64 sum is exact, so both modes give the same D_L.
 template <int L, int NB, bool FILTER>
 __device__ __forceinline__ int recipient_topk(const float* V, int sp, int sq, int Q, int s,
                                               int pg, int q0, int sign, int np, int k,
                                               double bound, float bound32, int lane,
-                                              double& ed, int& ei) {
+                                              const EstScratch& sc, double& ed, int& ei) {
   // batches in flight together (a divisor of NB): at most 24 staged values
   // per lane
   constexpr int NG = NB * L <= 24 ? NB : (NB % 2 == 0 && NB * L <= 48 ? NB / 2 : 1);
   const int step = sp + sq;
   ed = __builtin_huge_val();
   ei = INT_MAX;
-  bool empty = true;
+  int total = 0;        // entries in the scratch
+  bool listed = false;  // the entries are a sorted list in ed/ei instead
+  __builtin_amdgcn_wave_barrier();
 #pragma unroll
   for (int b0 = 0; b0 < NB; b0 += NG) {
     float w[NG][L];
@@ -144,32 +156,47 @@ __device__ __forceinline__ int recipient_topk(const float* V, int sp, int sq, in
       const bool valid = cand[b] & (D <= bound);
       const uint64_t vm = __ballot(valid);
       if (!vm) continue;
-      if (empty && __builtin_popcountll(vm) > 8) {
-        double d = valid ? D : __builtin_huge_val();
-        int c = valid ? qg : INT_MAX - 64 + lane;
+      if (!listed) {
+        const int cnt = __builtin_popcountll(vm);
+        if (total + cnt <= 64) {
+          const int pos = total + (int)__builtin_amdgcn_mbcnt_hi(
+                                      (uint32_t)(vm >> 32),
+                                      __builtin_amdgcn_mbcnt_lo((uint32_t)vm, 0));
+          if (valid) {
+            sc.d[pos] = D;
+            sc.i[pos] = qg;
+          }
+          total += cnt;
+          continue;
+        }
+        // the scratch would overflow: sort it into the list in registers
+        __builtin_amdgcn_wave_barrier();
+        double d = lane < total ? sc.d[lane] : __builtin_huge_val();
+        int c = lane < total ? sc.i[lane] : INT_MAX - 64 + lane;
+        __builtin_amdgcn_wave_barrier();
         bitonic_sort64(d, c, lane);
-        const bool real = c < INT_MAX - 64;  // the sorted entry is a candidate
+        const bool real = lane < (total < k ? total : k);
         ed = real ? d : __builtin_huge_val();
         ei = real ? c : INT_MAX;
-      } else {
-        const double kd = readlane_d(ed, k - 1);
-        const int ki = __builtin_amdgcn_readlane(ei, k - 1);
-        const bool pass = valid && key_less(D, qg, kd, ki);
-        const uint64_t m = __ballot(pass);
-        if (m) insert_reg(m, D, qg, k, ed, ei);
+        listed = true;
       }
-      empty = false;
+      const double kd = readlane_d(ed, k - 1);
+      const int ki = __builtin_amdgcn_readlane(ei, k - 1);
+      const uint64_t m = __ballot(valid && key_less(D, qg, kd, ki));
+      if (m) insert_reg(m, D, qg, k, ed, ei);
     }
   }
-  return __builtin_popcountll(__ballot(lane < k && ei != INT_MAX));
+  if (listed) return __builtin_popcountll(__ballot(lane < k && ei != INT_MAX));
+  __builtin_amdgcn_wave_barrier();
+  double d = lane < total ? sc.d[lane] : __builtin_huge_val();
+  int c = lane < total ? sc.i[lane] : INT_MAX - 64 + lane;
+  __builtin_amdgcn_wave_barrier();  // read before the next recipient writes the scratch
+  if (total > k) bitonic_sort64(d, c, lane);
+  const bool real = lane < (total < k ? total : k);
+  ed = real ? d : __builtin_huge_val();
+  ei = real ? c : INT_MAX;
+  return total < k ? total : k;
 }
-
-// Per-wave LDS scratch of the first round: up to 64 compacted candidates.
-struct EstScratch {
-  double* d;  // [64]
-  int* i;     // [64]
-};
-constexpr int EST_SCRATCH_BYTES = 64 * (sizeof(double) + sizeof(int));
 
 // The k-th smallest of the wave's 64 keys (bitonic network of lane exchanges
 // on the keys alone; keys are non-negative or +inf).
@@ -265,8 +292,8 @@ __device__ __forceinline__ int recipient_establish(const float* V, int sp, int s
   __builtin_amdgcn_wave_barrier();
   if (fallback || total > 64)
     return recipient_topk<L, NB, false>(V, sp, sq, Q, s, pg, q0, sign, np, k,
-                                        __builtin_huge_val(), __builtin_huge_valf(), lane, ed,
-                                        ei);
+                                        __builtin_huge_val(), __builtin_huge_valf(), lane, sc,
+                                        ed, ei);
   double d = lane < total ? sc.d[lane] : __builtin_huge_val();
   int c = lane < total ? sc.i[lane] : INT_MAX - 64 + lane;
   __builtin_amdgcn_wave_barrier();  // the scratch is read before the next recipient writes it
@@ -302,7 +329,7 @@ __device__ __forceinline__ void side_topk(const float* V, int sp, int sq, int Q,
       const float b32 = __builtin_bit_cast(
           float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, mybound32), u));
       const int n = recipient_topk<L, NB, true>(V, sp, sq, Q, s, pg, q0, sign, np, out.k, b,
-                                                b32, lane, ed, ei);
+                                                b32, lane, sc, ed, ei);
       slot_write(out, pg, slot, n, ed, ei, lane);
     }
   } else {
