@@ -410,25 +410,57 @@ __global__ __launch_bounds__(GRAM_THREADS, 1) void gram_kernel(
     float* V = (float*)lds;  // [staged][FPITCH]
     const int hs = fg.B / 2;                           // recipients per part
     const int Rs = hs + fg.L - 1;                      // staged rows (columns)
+    // the snapshot distances, once: d = -2 acc, clamped
+#pragma unroll
+    for (int bm = 0; bm < BM; ++bm)
+#pragma unroll
+      for (int bn = 0; bn < BN; ++bn)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[bm][bn][r] = clamp_distance(-2.f * acc[bm][bn][r]);
+    // accumulator r of a 32x32 block holds row 8 (r / 4) + 4 (lane / 32) + r % 4
+    // of the block, column lane % 32
+    const int lrow = 4 * (lane >> 5), lcol = lane & 31;
 #pragma unroll 1
     for (int part = 0; part < 4; ++part) {
       const bool cols = part >= 2;
       const int off = (part & 1) * hs;  // first staged tile row (column)
+      if (!cols) {
+        // rows off .. off + Rs - 1 of the tile, as staged rows
 #pragma unroll
-      for (int bm = 0; bm < BM; ++bm) {
-        const int rb = wm * WT_M + bm * 32;
-        if (!cols && (rb + 32 <= off || rb >= off + Rs)) continue;
+        for (int bm = 0; bm < BM; ++bm) {
+          const int rb = wm * WT_M + bm * 32;
+          if (rb + 32 <= off || rb >= off + Rs) continue;
+          const bool whole = rb >= off && rb + 32 <= off + Rs;  // every row of the block
+#pragma unroll
+          for (int bn = 0; bn < BN; ++bn) {
+            float* base = V + (rb - off + lrow) * FPITCH + wn * WT_N + bn * 32 + lcol;
+            if (whole) {
+#pragma unroll
+              for (int r = 0; r < 16; ++r) base[(8 * (r >> 2) + (r & 3)) * FPITCH] = acc[bm][bn][r];
+            } else {
+#pragma unroll
+              for (int r = 0; r < 16; ++r) {
+                const int dr = 8 * (r >> 2) + (r & 3);
+                const int rel = rb - off + lrow + dr;
+                if (rel >= 0 && rel < Rs) base[dr * FPITCH] = acc[bm][bn][r];
+              }
+            }
+          }
+        }
+      } else {
+        // columns off .. off + Rs - 1 of the tile, as staged rows (transposed)
 #pragma unroll
         for (int bn = 0; bn < BN; ++bn) {
           const int cb = wn * WT_N + bn * 32;
-          if (cols && (cb + 32 <= off || cb >= off + Rs)) continue;
-          const int col = cb + (lane & 31);
+          if (cb + 32 <= off || cb >= off + Rs) continue;
+          const int rel = cb + lcol - off;
+          if (rel >= 0 && rel < Rs) {
 #pragma unroll
-          for (int r = 0; r < 16; ++r) {
-            const int row = rb + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-            const int rel = (cols ? col : row) - off;
-            if (rel >= 0 && rel < Rs)
-              V[rel * FPITCH + (cols ? row : col)] = clamp_distance(-2.f * acc[bm][bn][r]);
+            for (int bm = 0; bm < BM; ++bm) {
+              float* base = V + rel * FPITCH + wm * WT_M + bm * 32 + lrow;
+#pragma unroll
+              for (int r = 0; r < 16; ++r) base[8 * (r >> 2) + (r & 3)] = acc[bm][bn][r];
+            }
           }
         }
       }
