@@ -125,15 +125,20 @@ __global__ __launch_bounds__(F64_THREADS) void fused_f64_kernel(
 // prefix sum, and the entries' positions parked in LDS (up to SEL_PARK at a
 // time), so that each lane then loads one entry and a ballot filters 64
 // entries against the list's k-th at once -- two memory round trips per
-// batch of slots.
+// batch of slots. A batch with many entries below the k-th is merged into the
+// list by one sort of both, the others by insertion.
 constexpr int SEL_WAVES = 4;
 constexpr int SEL_PARK = 1024;
+// a batch with at least this many entries to insert is merged by a sort
+constexpr int SEL_SORT_MIN = 6;
 template <bool FINAL>
 __global__ __launch_bounds__(64 * SEL_WAVES) void select_kernel(
     FusedGeom g, FusedSlots out, double* __restrict__ bound, double* __restrict__ run_d,
     int32_t* __restrict__ run_i, int hlo, int hhi, int32_t* __restrict__ idx,
     double* __restrict__ dist) {
   __shared__ int park[SEL_WAVES][SEL_PARK];  // (slot << 6 | entry) per entry
+  __shared__ double mrg_d[SEL_WAVES][64];    // a batch's entries to merge
+  __shared__ int mrg_i[SEL_WAVES][64];
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
   const int t = blockIdx.x * SEL_WAVES + w;
@@ -185,8 +190,34 @@ __global__ __launch_bounds__(64 * SEL_WAVES) void select_kernel(
         }
         const double kd = readlane_d(ed, k - 1);
         const int ki = __builtin_amdgcn_readlane(ei, k - 1);
-        const uint64_t m = __ballot(e < p1 && key_less(d, c, kd, ki));
-        if (m) insert_reg(m, d, c, k, ed, ei);
+        const bool pass = e < p1 && key_less(d, c, kd, ki);
+        const uint64_t m = __ballot(pass);
+        const int cnt = __builtin_popcountll(m);
+        if (cnt >= SEL_SORT_MIN && k + cnt <= 64) {
+          // the list (lanes < k) and the passing entries (compacted into
+          // lanes k ..) in one sort; its first k lanes are the new list
+          const int pos = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
+          if (pass) {
+            mrg_d[w][pos] = d;
+            mrg_i[w][pos] = c;
+          }
+          __builtin_amdgcn_wave_barrier();
+          const int src = lane - k;
+          double md = lane < k ? ed : __builtin_huge_val();
+          int mi = lane < k ? ei : INT_MAX - 64 + lane;
+          if (src >= 0 && src < cnt) {
+            md = mrg_d[w][src];
+            mi = mrg_i[w][src];
+          }
+          __builtin_amdgcn_wave_barrier();
+          bitonic_sort64(md, mi, lane);
+          const bool real = mi < INT_MAX - 64;
+          ed = real ? md : __builtin_huge_val();
+          ei = real ? mi : INT_MAX;
+        } else if (m) {
+          insert_reg(m, d, c, k, ed, ei);
+        }
       }
       __builtin_amdgcn_wave_barrier();
     }

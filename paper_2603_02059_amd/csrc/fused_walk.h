@@ -138,7 +138,9 @@ __device__ __forceinline__ int recipient_topk(const float* V, int sp, int sq, in
     for (int b = 0; b < NG; ++b) {
       const int q = 64 * (b0 + b) + lane;
       const int qg = q0 + q;
-      cand[b] = (q < Q) & (qg < np) & (sign * (qg - pg) >= L);
+      // the exclusion zone only reaches the first round's tiles (offsets 0
+      // and 1): a later round's pairs are more than a block apart
+      cand[b] = (q < Q) & (qg < np) & (FILTER || sign * (qg - pg) >= L);
       if constexpr (FILTER) {
         float s32 = w[b][0];
 #pragma unroll

@@ -59,6 +59,9 @@ inline int colstat_chunks(int64_t T) {
 constexpr int FUSED_F64_TILE = 128;
 constexpr int FUSED_ROUNDS = 4;
 constexpr int FUSED_ROUND_END[FUSED_ROUNDS - 1] = {2, 8, 32};  // the last round ends at nbt
+// later rounds (tile offsets 2 and up) hold no pair within the exclusion zone,
+// whose width L is below the block stride B, and their consumer skips its test
+static_assert(FUSED_ROUND_END[0] >= 2, "the first round covers tile offsets 0 and 1");
 struct FusedGeom {
   int T, np, L, k, B, nbt;
   int blo, bhi;  // the launch's offsets J - I: [blo, bhi)
