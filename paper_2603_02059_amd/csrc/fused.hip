@@ -21,7 +21,8 @@ namespace traknn {
 namespace {
 
 constexpr int F64_TILE = FUSED_F64_TILE;   // snapshot rows and columns of a tile
-constexpr int F64_THREADS = 256;
+constexpr int F64_THREADS = 512;
+constexpr int F64_ROWS = F64_TILE / (F64_THREADS / 64);  // Gram rows per wave
 constexpr int F64_KC = 16;                 // cells per K chunk staged in LDS
 constexpr int F64_LD = F64_TILE + 1;       // pitch of the staged distance tile (odd)
 constexpr int F64_APITCH = F64_KC + 1;     // pitch of the A panel, doubles
@@ -29,7 +30,8 @@ constexpr int F64_BPITCH = F64_TILE + 2;   // pitch of the transposed B panel, d
 constexpr int F64_PANEL_BYTES = (F64_TILE * F64_APITCH + F64_KC * F64_BPITCH) * 8;
 constexpr int F64_VAL_BYTES = F64_TILE * F64_LD * 4;
 constexpr int F64_UNION_BYTES = F64_PANEL_BYTES > F64_VAL_BYTES ? F64_PANEL_BYTES : F64_VAL_BYTES;
-static_assert(F64_TILE == 128, "the Gram mapping gives each wave 32 rows and each lane 2 columns");
+static_assert(F64_TILE == 128 && F64_ROWS == 16,
+              "the Gram mapping gives each wave 16 rows and each lane 2 columns");
 
 // Eq. 4 in FP64 from the two squared norms and the inner product: one rounding.
 __device__ __forceinline__ double f64_dist(double ni, double nj, double g) {
@@ -56,12 +58,12 @@ __global__ __launch_bounds__(F64_THREADS) void fused_f64_kernel(
   double* Ap = (double*)un;                    // [F64_TILE][F64_APITCH]
   double* Bt = Ap + F64_TILE * F64_APITCH;     // [F64_KC][F64_BPITCH]
 
-  // Gram of the tile: wave w owns rows 32w .. 32w + 31 (read as broadcasts),
+  // Gram of the tile: wave w owns rows 16w .. 16w + 15 (read as broadcasts),
   // each lane the columns lane and lane + 64.
-  double acc[32][2];
+  double acc[F64_ROWS][2];
 #pragma unroll
-  for (int r = 0; r < 32; ++r) acc[r][0] = acc[r][1] = 0.0;
-  double nacc = 0.0;  // thread t < 128: A row t, t >= 128: B row t - 128
+  for (int r = 0; r < F64_ROWS; ++r) acc[r][0] = acc[r][1] = 0.0;
+  double nacc = 0.0;  // thread t < 128: A row t, 128 <= t < 256: B row t - 128
   for (int k0 = 0; k0 < D; k0 += F64_KC) {
     __syncthreads();  // previous chunk fully read
     for (int e = tid; e < F64_TILE * F64_KC; e += F64_THREADS) {
@@ -70,7 +72,7 @@ __global__ __launch_bounds__(F64_THREADS) void fused_f64_kernel(
       Bt[c * F64_BPITCH + r] = centred(X, ldx, g.T, D, mu, j0 + r, k0 + c);
     }
     __syncthreads();
-    {
+    if (tid < 2 * F64_TILE) {
       const bool a_side = tid < F64_TILE;
       const int r = a_side ? tid : tid - F64_TILE;
 #pragma unroll
@@ -84,19 +86,19 @@ __global__ __launch_bounds__(F64_THREADS) void fused_f64_kernel(
       const double b0 = Bt[c * F64_BPITCH + lane];
       const double b1 = Bt[c * F64_BPITCH + lane + 64];
 #pragma unroll
-      for (int r = 0; r < 32; ++r) {
-        const double a = Ap[(32 * w + r) * F64_APITCH + c];
+      for (int r = 0; r < F64_ROWS; ++r) {
+        const double a = Ap[(F64_ROWS * w + r) * F64_APITCH + c];
         acc[r][0] = __builtin_fma(a, b0, acc[r][0]);
         acc[r][1] = __builtin_fma(a, b1, acc[r][1]);
       }
     }
   }
-  nrm[tid >> 7][tid & (F64_TILE - 1)] = nacc;
+  if (tid < 2 * F64_TILE) nrm[tid >> 7][tid & (F64_TILE - 1)] = nacc;
   __syncthreads();  // panels read, norms written
   float* V = (float*)un;  // [F64_TILE][F64_LD] snapshot distances of the tile
 #pragma unroll
-  for (int r = 0; r < 32; ++r) {
-    const int a = 32 * w + r;
+  for (int r = 0; r < F64_ROWS; ++r) {
+    const int a = F64_ROWS * w + r;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int b = lane + 64 * h;
@@ -104,12 +106,14 @@ __global__ __launch_bounds__(F64_THREADS) void fused_f64_kernel(
     }
   }
   __syncthreads();
-  // The row side (recipients = the tile's rows, slot J + 1) on waves 0-1 and
-  // the column side (recipients = its columns, slot I) on waves 2-3.
-  const int side = w >> 1;
+  // The row side (recipients = the tile's rows, slot J + 1) on the first half
+  // of the waves, the column side (recipients = its columns, slot I) on the
+  // second.
+  constexpr int NW = F64_THREADS / 64;
+  const int side = w / (NW / 2);
   side_topk_len<F64_TILE / 64, ESTABLISH>(g.L, V, side ? 1 : F64_LD, side ? F64_LD : 1, g.B, g.B,
                                (int)(side ? j0 : i0), (int)(side ? i0 : j0), side ? -1 : 1,
-                               side ? I : J + 1, g.np, w & 1, 2, lane,
+                               side ? I : J + 1, g.np, w % (NW / 2), NW / 2, lane,
                                bound, out, EstScratch{est_d[w], est_i[w]});
 }
 
