@@ -58,8 +58,8 @@ __global__ __launch_bounds__(F64_THREADS) void fused_f64_kernel(
   double* Ap = (double*)un;                    // [F64_TILE][F64_APITCH]
   double* Bt = Ap + F64_TILE * F64_APITCH;     // [F64_KC][F64_BPITCH]
 
-  // Gram of the tile: wave w owns rows 16w .. 16w + 15 (read as broadcasts),
-  // each lane the columns lane and lane + 64.
+  // Gram of the tile: wave w owns the F64_ROWS rows from F64_ROWS w on (read
+  // as broadcasts), each lane the columns lane and lane + 64.
   double acc[F64_ROWS][2];
 #pragma unroll
   for (int r = 0; r < F64_ROWS; ++r) acc[r][0] = acc[r][1] = 0.0;
