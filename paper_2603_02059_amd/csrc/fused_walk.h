@@ -18,14 +18,15 @@
 // Every (recipient, tile side) writes the list of its candidates it keeps --
 // at most k -- to its own slot (FusedSlots), and a select kernel takes the k
 // nearest over a row's slots. Each recipient is handled by one wave (lane =
-// candidate), so its list lives in registers: nothing goes through atomics
-// and nothing can overflow.
+// candidate), which gathers its candidates in registers and in its own LDS
+// scratch: nothing goes through global atomics and nothing can overflow.
 //  * ESTABLISH (the first round, the tiles nearest the diagonal): a recipient
 //    keeps its exact k nearest in the tile. A refresh then takes each row's
 //    k-th over these slots: an upper bound of its true k-th distance.
 //  * FILTER (every later round): a recipient keeps the k nearest of its
 //    candidates within its bound. A true neighbour is never above the bound,
-//    so the slots always contain the k nearest.
+//    so the slots always contain the k nearest. These rounds' tiles lie two
+//    or more blocks from the diagonal, so no pair is in the exclusion zone.
 #pragma once
 
 #include "internal.h"
