@@ -112,6 +112,37 @@ void plan_fused(traknn_plan_s* p) {
   if (!f64) g.B = g.B / 4 * 4;  // 16-byte aligned chunk-norm loads of each panel
   g.nbt = (int)((g.np + g.B - 1) / g.B);
   g.blo = g.bhi = 0;
+  // Round ends: each launch's last wave of tiles is partly idle, so the
+  // second and third rounds end where the four launches need the fewest
+  // waves of resident tiles, ties kept nearest the default ends.
+  const int64_t conc = (int64_t)NUM_CU * (f64 ? FUSED_F64_PER_CU : 1);
+  auto tiles = [&](int lo, int hi) {
+    hi = hi < g.nbt ? hi : g.nbt;
+    int64_t n = 0;
+    for (int h = lo; h < hi; ++h) n += g.nbt - h;
+    return n;
+  };
+  auto waves = [&](int lo, int hi) { return (tiles(lo, hi) + conc - 1) / conc; };
+  auto cost = [&](int e2, int e3) {
+    return waves(0, FUSED_FIRST_END) + waves(FUSED_FIRST_END, e2) + waves(e2, e3) +
+           waves(e3, g.nbt);
+  };
+  auto dist = [&](int e2, int e3) {
+    const int a = e2 - FUSED_END_DEFAULT[0], b = e3 - FUSED_END_DEFAULT[1];
+    return 4 * (a < 0 ? -a : a) + (b < 0 ? -b : b);
+  };
+  g.rend[0] = FUSED_END_DEFAULT[0];
+  g.rend[1] = FUSED_END_DEFAULT[1];
+  int64_t best = cost(g.rend[0], g.rend[1]);
+  for (int e2 = 6; e2 <= 12; ++e2)
+    for (int e3 = e2 + 4 > 24 ? e2 + 4 : 24; e3 <= 48; ++e3) {
+      const int64_t cst = cost(e2, e3);
+      if (cst < best || (cst == best && dist(e2, e3) < dist(g.rend[0], g.rend[1]))) {
+        best = cst;
+        g.rend[0] = e2;
+        g.rend[1] = e3;
+      }
+    }
   // the MFMA tiles read a full 256-row panel from every block-row's start
   if (!f64) {
     const int64_t need = (int64_t)(g.nbt - 1) * g.B + GRAM_TILE;
@@ -217,7 +248,7 @@ int enqueue_fused(traknn_plan_s* plan, const float* X, int64_t ldx, void* worksp
   int rc;
   int lo = 0;
   for (int r = 0; r < FUSED_ROUNDS && lo < g.nbt; ++r) {
-    int hi = r + 1 < FUSED_ROUNDS ? FUSED_ROUND_END[r] : g.nbt;
+    int hi = r == 0 ? FUSED_FIRST_END : r + 1 < FUSED_ROUNDS ? g.rend[r - 1] : g.nbt;
     if (hi > g.nbt) hi = g.nbt;
     g.blo = lo;
     g.bhi = hi;

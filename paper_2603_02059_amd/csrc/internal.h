@@ -52,19 +52,28 @@ inline int colstat_chunks(int64_t T) {
 // trajectories (rounded down to a multiple of 4 for the MFMA tiles) with B,
 // so consecutive tiles overlap by L - 1 fields; nbt = ceil(n' / B)
 // block-rows. The tiles run in rounds of offsets J - I: the first,
-// [0, FUSED_ROUND_END[0]), keeps each recipient's exact k nearest per tile
+// [0, FUSED_FIRST_END), keeps each recipient's exact k nearest per tile
 // (no bound yet); every later round, [blo, bhi), keeps only the candidates
 // within each row's bound, which a refresh after each round lowers to the
 // k-th of everything seen so far.
 constexpr int FUSED_F64_TILE = 128;
 constexpr int FUSED_ROUNDS = 4;
-constexpr int FUSED_ROUND_END[FUSED_ROUNDS - 1] = {2, 8, 32};  // the last round ends at nbt
-// later rounds (tile offsets 2 and up) hold no pair within the exclusion zone,
-// whose width L is below the block stride B, and their consumer skips its test
-static_assert(FUSED_ROUND_END[0] >= 2, "the first round covers tile offsets 0 and 1");
+// The first round is offsets [0, 2). Later rounds (tile offsets 2 and up)
+// hold no pair within the exclusion zone, whose width L is below the block
+// stride B, and their consumer skips its test.
+constexpr int FUSED_FIRST_END = 2;
+static_assert(FUSED_FIRST_END >= 2, "the first round covers tile offsets 0 and 1");
+// Ends of the second and third rounds: by default 8 and 32; the planner moves
+// them within [6, 12] and [24, 48] to fill the launches' last waves of tiles.
+constexpr int FUSED_END_DEFAULT[2] = {8, 32};
+// Compute units of an MI355X: the tiles resident at once are this many times
+// the workgroups of a fused tile kernel per CU (1 MFMA, 2 FP64).
+constexpr int NUM_CU = 256;
+constexpr int FUSED_F64_PER_CU = 2;
 struct FusedGeom {
   int T, np, L, k, B, nbt;
   int blo, bhi;  // the launch's offsets J - I: [blo, bhi)
+  int rend[2];   // ends of the second and third rounds
 };
 // Per-row slots of candidate lists: row t meets exactly nbt + 1 tile-sides
 // (the column sides of tiles (I', I_t), I' <= I_t, in slots I'; the row sides
