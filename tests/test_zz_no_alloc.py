@@ -28,12 +28,12 @@ def test_noalloc_rejects_plans_beyond_its_scratch():
         tk.traknn_plan_destroy(h)
 
 
-def _both(Xn, L, k, prec):
+def _both(Xn, L, k, prec, mode="matrix"):
     """(workspace entry point outputs, allocation-free entry point outputs)."""
     import torch
     T, D = Xn.shape
     X = torch.from_numpy(np.ascontiguousarray(Xn)).cuda()
-    p = tk.Plan(T, D, L, L, k, prec)
+    p = tk.Plan(T, D, L, L, k, prec, mode=mode)
     assert p.ws_bytes <= tk.NOALLOC_MAX_BYTES
     i1, d1 = p.empty_outputs()
     i2, d2 = p.empty_outputs()
@@ -64,3 +64,25 @@ def test_noalloc_matches_knn_twice_then_smaller():
         Dm = oracle.traj_dist(Xn, L)
         check_rows(Xn, L, k, np.arange(n), i2[0], d2[0], s2[0], precision_tol(prec),
                    ref=(ref[0], ref[1], ref[2], ref[3], Dm), label="noalloc")
+
+
+@pytest.mark.gpu
+def test_noalloc_fused_matches_knn():
+    """The fused mode through the allocation-free entry point: its slots,
+    bounds and running lists live in the fixed scratch, which keeps the
+    previous call's contents, so every slot must be written before it is
+    read. A larger series, then a smaller one, in FP64 and BF16x3."""
+    print("[gpu] noalloc: fused mode", flush=True)
+    Xa, _ = synth.make_fields(1400, 4, 8, sigma=1.0, n_events=3, event_len=5, seed=23)
+    Xb, _ = synth.make_fields(700, 4, 8, sigma=1.0, n_events=2, event_len=5, seed=29)
+    for Xn, prec in ((Xa, "fp64"), (Xb, "fp64"), (Xa, "bf16x3"), (Xb, "bf16x3")):
+        L, k = 5, 8
+        print(f"  T={Xn.shape[0]} D={Xn.shape[1]} L={L} k={k} {prec} fused", flush=True)
+        i1, d1, i2, d2, s2 = _both(Xn, L, k, prec, mode="fused")
+        assert np.array_equal(i1, i2) and np.array_equal(d1, d2)
+        if prec == "fp64":
+            n = Xn.shape[0] - L + 1
+            ref = oracle.knn(Xn, L, k)
+            Dm = oracle.traj_dist(Xn, L)
+            check_rows(Xn, L, k, np.arange(n), i2[0], d2[0], s2[0], 1e-5,
+                       ref=(ref[0], ref[1], ref[2], ref[3], Dm), label="noalloc fused")
