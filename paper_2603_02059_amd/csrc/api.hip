@@ -97,8 +97,8 @@ bool plan_window(traknn_plan_s* p) {
   return p->win_splits > 0 && (!p->rb || p->col_splits > 0);
 }
 
-// Fused mode: tile stride and block-rows (the rounds of offsets are set per
-// launch).
+// Fused mode: tile stride, block-rows and the ends of the second and third
+// rounds of tile offsets (each launch then covers one round).
 void plan_fused(traknn_plan_s* p) {
   const traknn_config& c = p->cfg;
   FusedGeom& g = p->fg;
