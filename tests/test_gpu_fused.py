@@ -160,11 +160,12 @@ def test_fused_mfma_equals_matrix(T, D, L, k, prec):
     _say(f"  {st}")
 
 
-@pytest.mark.parametrize("shape,prec", [("full", "bf16x3"), ("grid32", "bf16x3")])
+@pytest.mark.parametrize("shape,prec", [("full", "bf16x3"), ("grid32", "bf16x3"),
+                                        ("pca13", "bf16x3")])
 def test_fused_mfma_full_length_equals_matrix(shape, prec):
-    """At T = 27394: the headline workload (D = 8192) and the 4 x 8 grid, L = 5,
-    k = 10, the fused mode equals the matrix mode bit for bit on every row,
-    and sampled rows match the oracle."""
+    """At T = 27394: the headline workload (D = 8192), the 4 x 8 grid and the
+    13-component PCA shape, L = 5, k = 10, the fused mode equals the matrix
+    mode bit for bit on every row, and sampled rows match the oracle."""
     from tests.parity import gram_norm_tol, precision_tol
     T, L, k = 27394, 5, 10
     if shape not in _DATA:
@@ -172,6 +173,9 @@ def test_fused_mfma_full_length_equals_matrix(shape, prec):
         if shape == "grid32":
             _DATA[shape] = synth.make_fields(T, 4, 8, sigma=1.0, n_events=20, event_len=5,
                                              seed=4)
+        elif shape == "pca13":
+            Z, zstarts, _ = synth.make_pca_workload(13)
+            _DATA[shape] = (Z, zstarts)
         else:
             _DATA[shape] = synth.make_workload("full")
     Xn, starts = _DATA[shape]
