@@ -484,7 +484,8 @@ __global__ __launch_bounds__(GRAM_THREADS, 1) void gram_kernel(
   // each 32-row band (bm) of every wave is parked column-major in LDS with
   // compile-time accumulator indices, then all threads write the band's
   // distances coalesced: rows of S for (i, j), and 128-byte runs of S rows for
-  // the mirrored (j, i).
+  // the mirrored (j, i). The whole-matrix mode writes them non-temporally: S is
+  // read back only after the Gram, far too large for the caches.
   constexpr int NWAVES = GRAM_THREADS / 64;
   float* stg = (float*)lds;  // [NWAVES][WT_N][EPI_PITCH]
   const bool diag = !BAND && I == J;
@@ -521,7 +522,10 @@ __global__ __launch_bounds__(GRAM_THREADS, 1) void gram_kernel(
             const float v = -2.f * src[r];
             // band mode: a field's distance to itself is stored as 0, as the
             // mirrored pass stores it in the symmetric mode
-            S[i * ldS + (j - c0)] = (BAND && a_row0 + i == j) ? 0.f : clamp_distance(v);
+            if constexpr (BAND)
+              S[i * ldS + (j - c0)] = a_row0 + i == j ? 0.f : clamp_distance(v);
+            else  // the whole matrix is read back only after the Gram: stream it
+              __builtin_nontemporal_store(clamp_distance(v), &S[i * ldS + j]);
           }
         }
       }
@@ -558,7 +562,7 @@ __global__ __launch_bounds__(GRAM_THREADS, 1) void gram_kernel(
         } else {
           float* dst = S + j * ldS + i0;
           if (!diag && i0 + 3 < T) {
-            *(f32x4*)dst = f32x4{f[0], f[1], f[2], f[3]};
+            __builtin_nontemporal_store(f32x4{f[0], f[1], f[2], f[3]}, (f32x4*)dst);
           } else {
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
