@@ -514,18 +514,23 @@ __global__ __launch_bounds__(GRAM_THREADS, 1) void gram_kernel(
       if (j < T) {
         for (int wm_ = tid / TILE; wm_ < WAVES_M; wm_ += GRAM_THREADS / TILE) {
           const float* src = stg + (wm_ * WAVES_N + wn_) * WT_N * EPI_PITCH + c * EPI_PITCH;
-          for (int r = 0; r < 32; ++r) {
-            const int il = wm_ * 128 + bm * 32 + r;
-            const int64_t i = i_base + il;
-            if (i >= rows_out) break;
-            if (diag && il >= jl) continue;  // diagonal tile: strict upper half
-            const float v = -2.f * src[r];
-            // band mode: a field's distance to itself is stored as 0, as the
-            // mirrored pass stores it in the symmetric mode
+          const int il0 = wm_ * 128 + bm * 32;
+          const int64_t i0 = i_base + il0;
+          // rows written: those below rows_out and, on a diagonal tile, above
+          // the diagonal (il < jl); the row pointer steps by ldS
+          int64_t nr = rows_out - i0;
+          if (diag && jl - il0 < nr) nr = jl - il0;
+          const int n = nr < 32 ? (int)nr : 32;
+          float* dst = S + i0 * ldS + (j - c0);
+          // band mode: a field's distance to itself is stored as 0, as the
+          // mirrored pass stores it in the symmetric mode
+          const int64_t dz = BAND ? j - (a_row0 + i0) : -1;
+          for (int r = 0; r < n; ++r, dst += ldS) {
+            const float v = clamp_distance(-2.f * src[r]);
             if constexpr (BAND)
-              S[i * ldS + (j - c0)] = a_row0 + i == j ? 0.f : clamp_distance(v);
+              *dst = r == dz ? 0.f : v;
             else  // the whole matrix is read back only after the Gram: stream it
-              __builtin_nontemporal_store(clamp_distance(v), &S[i * ldS + j]);
+              __builtin_nontemporal_store(v, dst);
           }
         }
       }
