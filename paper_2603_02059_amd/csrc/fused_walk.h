@@ -86,6 +86,10 @@ __device__ __forceinline__ float prefilter_bound(double bound) {
   return f;
 }
 
+// LLVM's predicate code of an ordered <= (false on NaN), for the compare
+// builtins that return the wave's lane mask directly
+constexpr int FCMP_OLE = 5;
+
 // Per-wave LDS scratch of a recipient's candidates: up to 64 compacted entries.
 struct EstScratch {
   double* d;  // [64]
@@ -93,10 +97,25 @@ struct EstScratch {
 };
 constexpr int EST_SCRATCH_BYTES = 64 * (sizeof(double) + sizeof(int));
 
+// Lane masks of the candidates of each batch of 64 (lane = candidate q of
+// q0 + 64 b ..): q < Q and q0 + q < np and, for a recipient pg given
+// (pg >= 0), outside its exclusion zone (sign (q0 + q - pg) >= L).
+template <int NB>
+__device__ __forceinline__ void batch_masks(int Q, int q0, int np, int pg, int sign, int L,
+                                            int lane, uint64_t (&rng)[NB]) {
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int q = 64 * b + lane;
+    const int qg = q0 + q;
+    rng[b] = __builtin_amdgcn_ballot_w64((q < Q) & (qg < np) &
+                                         (pg < 0 || sign * (qg - pg) >= L));
+  }
+}
+
 // The k nearest candidates within `bound` (+inf: all) of recipient s, from
 // direct L-term sums (Eq. 2) over the staged values. The candidates come 64
-// at a time (lane = candidate); the NB batches of the recipient (Q <= 64 NB)
-// are loaded before their ballots, as many at once as 24 staged values per
+// at a time (lane = candidate), those of batch b in rng[b]; the NB batches of
+// the recipient (Q <= 64 NB) are loaded before their ballots, as many at once as 24 staged values per
 // lane allow, so a recipient costs one or two LDS round trips. With a finite
 // bound (FILTER) each batch is first tested on its FP32 sums against bound32
 // (prefilter_bound): a candidate whose FP64 sum is within the bound always
@@ -112,7 +131,7 @@ constexpr int EST_SCRATCH_BYTES = 64 * (sizeof(double) + sizeof(int));
 // about 29 bits every FP64 sum is exact, so both modes give the same D_L.
 template <int L, int NB, bool FILTER>
 __device__ __forceinline__ int recipient_topk(const float* V, int sp, int sq, int Q, int s,
-                                              int pg, int q0, int sign, int np, int k,
+                                              int q0, const uint64_t (&rng)[NB], int k,
                                               double bound, float bound32, int lane,
                                               const EstScratch& sc, double& ed, int& ei) {
   // batches in flight together (a divisor of NB): at most 24 staged values
@@ -134,31 +153,29 @@ __device__ __forceinline__ int recipient_topk(const float* V, int sp, int sq, in
 #pragma unroll
       for (int m = 0; m < L; ++m) w[b][m] = v[m * step];
     }
-    bool cand[NG];  // in range, outside the exclusion zone (and, FILTER, FP32 sum within)
+    // the batches' candidates as wave masks (FILTER: FP32 sum within); the
+    // compares give their lane masks directly, with no per-lane flag
+    uint64_t cm[NG];
 #pragma unroll
     for (int b = 0; b < NG; ++b) {
-      const int q = 64 * (b0 + b) + lane;
-      const int qg = q0 + q;
-      // the exclusion zone only reaches the first round's tiles (offsets 0
-      // and 1): a later round's pairs are more than a block apart
-      cand[b] = (q < Q) & (qg < np) & (FILTER || sign * (qg - pg) >= L);
+      cm[b] = rng[b0 + b];
       if constexpr (FILTER) {
         float s32 = w[b][0];
 #pragma unroll
         for (int m = 1; m < L; ++m) s32 += w[b][m];
-        cand[b] = cand[b] & (s32 <= bound32);
+        cm[b] &= __builtin_amdgcn_fcmpf(s32, bound32, FCMP_OLE);
       }
     }
 #pragma unroll
     for (int b = 0; b < NG; ++b) {
-      if (!__ballot(cand[b])) continue;
+      if (!cm[b]) continue;
       const int qg = q0 + 64 * (b0 + b) + lane;
       double D = (double)w[b][0];
 #pragma unroll
       for (int m = 1; m < L; ++m) D += (double)w[b][m];
-      const bool valid = cand[b] & (D <= bound);
-      const uint64_t vm = __ballot(valid);
+      const uint64_t vm = cm[b] & __builtin_amdgcn_fcmp(D, bound, FCMP_OLE);
       if (!vm) continue;
+      const bool valid = (vm >> lane) & 1;
       if (!listed) {
         const int cnt = __builtin_popcountll(vm);
         if (total + cnt <= 64) {
@@ -243,11 +260,8 @@ __device__ __forceinline__ int recipient_establish(const float* V, int sp, int s
       for (int m = 0; m < L; ++m) w[b][m] = v[m * step];
     }
   };
-  auto is_cand = [&](int b) __attribute__((always_inline)) {
-    const int q = 64 * b + lane;
-    const int qg = q0 + q;
-    return (q < Q) & (qg < np) & (sign * (qg - pg) >= L);
-  };
+  uint64_t rng[NB];  // the recipient's candidates, outside its exclusion zone
+  batch_masks<NB>(Q, q0, np, pg, sign, L, lane, rng);
   float mn = __builtin_huge_valf();
 #pragma unroll
   for (int b0 = 0; b0 < NB; b0 += NG) {
@@ -258,7 +272,7 @@ __device__ __forceinline__ int recipient_establish(const float* V, int sp, int s
       float s32 = w[b][0];
 #pragma unroll
       for (int m = 1; m < L; ++m) s32 += w[b][m];
-      if (is_cand(b0 + b)) mn = __builtin_fminf(mn, s32);
+      if ((rng[b0 + b] >> lane) & 1) mn = __builtin_fminf(mn, s32);
     }
   }
   const float tau = kth_smallest64(mn, lane, k);
@@ -276,13 +290,13 @@ __device__ __forceinline__ int recipient_establish(const float* V, int sp, int s
       float s32 = w[b][0];
 #pragma unroll
       for (int m = 1; m < L; ++m) s32 += w[b][m];
-      bool c = is_cand(b0 + b) & (s32 <= b32);
-      if (!__ballot(c)) continue;
+      const uint64_t cm = rng[b0 + b] & __builtin_amdgcn_fcmpf(s32, b32, FCMP_OLE);
+      if (!cm) continue;
       double D = (double)w[b][0];
 #pragma unroll
       for (int m = 1; m < L; ++m) D += (double)w[b][m];
-      c = c & (D <= b64);
-      const uint64_t mk = __ballot(c);
+      const uint64_t mk = cm & __builtin_amdgcn_fcmp(D, b64, FCMP_OLE);
+      const bool c = (mk >> lane) & 1;
       const int pos = total + (int)__builtin_amdgcn_mbcnt_hi(
                                   (uint32_t)(mk >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0));
       if (c && pos < 64) {
@@ -294,9 +308,8 @@ __device__ __forceinline__ int recipient_establish(const float* V, int sp, int s
   }
   __builtin_amdgcn_wave_barrier();
   if (fallback || total > 64)
-    return recipient_topk<L, NB, false>(V, sp, sq, Q, s, pg, q0, sign, np, k,
-                                        __builtin_huge_val(), __builtin_huge_valf(), lane, sc,
-                                        ed, ei);
+    return recipient_topk<L, NB, false>(V, sp, sq, Q, s, q0, rng, k, __builtin_huge_val(),
+                                        __builtin_huge_valf(), lane, sc, ed, ei);
   double d = lane < total ? sc.d[lane] : __builtin_huge_val();
   int c = lane < total ? sc.i[lane] : INT_MAX - 64 + lane;
   __builtin_amdgcn_wave_barrier();  // the scratch is read before the next recipient writes it
@@ -322,6 +335,10 @@ __device__ __forceinline__ void side_topk(const float* V, int sp, int sq, int Q,
     const int pl = p0 + wave + lane * nw;  // lane u: the wave's u-th recipient
     const double mybound = (wave + lane * nw < P && pl < np) ? bound[pl] : -1.0;
     const float mybound32 = prefilter_bound(mybound);
+    // the filter rounds' tiles lie past the exclusion zone: the masks hold
+    // for every recipient
+    uint64_t rng[NB];
+    batch_masks<NB>(Q, q0, np, -1, sign, L, lane, rng);
     int u = 0;
     for (int s = wave; s < P; s += nw, ++u) {
       const int pg = p0 + s;
@@ -331,8 +348,8 @@ __device__ __forceinline__ void side_topk(const float* V, int sp, int sq, int Q,
       const double b = readlane_d(mybound, u);
       const float b32 = __builtin_bit_cast(
           float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, mybound32), u));
-      const int n = recipient_topk<L, NB, true>(V, sp, sq, Q, s, pg, q0, sign, np, out.k, b,
-                                                b32, lane, sc, ed, ei);
+      const int n = recipient_topk<L, NB, true>(V, sp, sq, Q, s, q0, rng, out.k, b, b32, lane,
+                                                sc, ed, ei);
       slot_write(out, pg, slot, n, ed, ei, lane);
     }
   } else {
