@@ -218,17 +218,26 @@ __device__ __forceinline__ int recipient_topk(const float* V, int sp, int sq, in
   return total < k ? total : k;
 }
 
-// The k-th smallest of the wave's 64 keys (bitonic network of lane exchanges
-// on the keys alone; keys are non-negative or +inf).
+// Bitonic network over the wave's 64 keys alone (keys are non-negative or
+// +inf): one merge of strides S, S / 2, ... 1, then the next block size.
+template <int SIZE, int S>
+__device__ __forceinline__ float sort_keys_merge64(float key, int lane) {
+  const float p = __builtin_bit_cast(float, lane_xor<S>(__builtin_bit_cast(int, key), lane));
+  const bool keep_min = ((lane & S) == 0) == ((lane & SIZE) == 0);
+  key = keep_min ? __builtin_fminf(key, p) : __builtin_fmaxf(key, p);
+  if constexpr (S > 1) return sort_keys_merge64<SIZE, S / 2>(key, lane);
+  return key;
+}
+template <int SIZE = 2>
+__device__ __forceinline__ float sort_keys64(float key, int lane) {
+  key = sort_keys_merge64<SIZE, SIZE / 2>(key, lane);
+  if constexpr (SIZE < 64) return sort_keys64<SIZE * 2>(key, lane);
+  return key;
+}
+
+// The k-th smallest of the wave's 64 keys.
 __device__ __forceinline__ float kth_smallest64(float key, int lane, int k) {
-#pragma unroll
-  for (int size = 2; size <= 64; size <<= 1)
-#pragma unroll
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      const float p = __shfl_xor(key, stride, 64);
-      const bool keep_min = ((lane & stride) == 0) == ((lane & size) == 0);
-      key = keep_min ? __builtin_fminf(key, p) : __builtin_fmaxf(key, p);
-    }
+  key = sort_keys64(key, lane);
   return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, key), k - 1));
 }
 

@@ -76,10 +76,65 @@ __device__ __forceinline__ void insert_seq(uint64_t mask, double D, int col, int
   }
 }
 
+// The value v of lane (lane ^ S), S a power of two up to 32. Strides up to
+// 8 stay inside rows of 16 lanes and use DPP moves, which are plain vector
+// ALU operations: quad permutes for 1 and 2; row rotations for 8 (by 8) and
+// for 4 (by 12 where bit 2 of the lane is clear, giving lane + 4, else by 4,
+// giving lane - 4). 16 uses a swizzle within 32 lanes and 32 a permute, both
+// through the LDS crossbar. Every lane of the wave must be active.
+template <int S>
+__device__ __forceinline__ int lane_xor(int v, int lane) {
+  static_assert(S == 1 || S == 2 || S == 4 || S == 8 || S == 16 || S == 32, "stride");
+  if constexpr (S == 1) {
+    return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+  } else if constexpr (S == 2) {
+    return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
+  } else if constexpr (S == 4) {
+    const int up = __builtin_amdgcn_mov_dpp(v, 0x12C, 0xF, 0xF, false);  // row_ror:12
+    const int dn = __builtin_amdgcn_mov_dpp(v, 0x124, 0xF, 0xF, false);  // row_ror:4
+    return (lane & 4) ? dn : up;
+  } else if constexpr (S == 8) {
+    return __builtin_amdgcn_mov_dpp(v, 0x128, 0xF, 0xF, false);  // row_ror:8
+  } else if constexpr (S == 16) {
+    return __builtin_amdgcn_ds_swizzle(v, (16 << 10) | 0x1F);  // bit mode, xor mask 16
+  } else {
+    return __builtin_amdgcn_ds_bpermute((lane ^ 32) << 2, v);
+  }
+}
+
+// One merge of a bitonic network over the wave: compare-exchange with the
+// lane S apart, then S / 2, ... 1; blocks of SIZE lanes end ascending where
+// bit SIZE of the lane is clear, descending elsewhere.
+template <int SIZE, int S>
+__device__ __forceinline__ void bitonic_merge64(double& d, int& c, int lane) {
+  const double pd = __hiloint2double(lane_xor<S>(__double2hiint(d), lane),
+                                     lane_xor<S>(__double2loint(d), lane));
+  const int pc = lane_xor<S>(c, lane);
+  const bool asc = (lane & SIZE) == 0;
+  const bool lower = (lane & S) == 0;
+  if ((lower == asc) == key_less(pd, pc, d, c)) {
+    d = pd;
+    c = pc;
+  }
+  if constexpr (S > 1) bitonic_merge64<SIZE, S / 2>(d, c, lane);
+}
+
 // Sort the wave's 64 keys (d, c) ascending by (distance, index) across the
 // lanes: afterwards lane r holds the r-th smallest (bitonic network of lane
-// exchanges). Keys must be distinct for a unique result.
+// exchanges, unrolled so that every stride is a compile-time constant). Keys
+// must be distinct for a unique result; every lane must be active.
+template <int SIZE = 2>
 __device__ __forceinline__ void bitonic_sort64(double& d, int& c, int lane) {
+  bitonic_merge64<SIZE, SIZE / 2>(d, c, lane);
+  if constexpr (SIZE < 64) bitonic_sort64<SIZE * 2>(d, c, lane);
+}
+
+// The same sort as a loop over run-time strides, each exchange a permute
+// through the LDS crossbar: slower per sort, but compact and light on
+// registers, for kernels that sort once per wave (the window's list seeds).
+// In the window kernels the unrolled network costs 4 registers, one wave per
+// SIMD and, with two lengths, spills.
+__device__ __forceinline__ void bitonic_sort64_compact(double& d, int& c, int lane) {
 #pragma unroll 1
   for (int size = 2; size <= 64; size <<= 1)
 #pragma unroll 1
@@ -88,8 +143,7 @@ __device__ __forceinline__ void bitonic_sort64(double& d, int& c, int lane) {
       const int pc = __shfl_xor(c, stride, 64);
       const bool asc = (lane & size) == 0;
       const bool lower = (lane & stride) == 0;
-      const bool p_less = key_less(pd, pc, d, c);
-      if ((lower == asc) == p_less) {
+      if ((lower == asc) == key_less(pd, pc, d, c)) {
         d = pd;
         c = pc;
       }
@@ -106,7 +160,7 @@ __device__ __forceinline__ void seed_row(double d, int c, bool valid, int k, dou
     d = __builtin_huge_val();
     c = INT_MAX - 64 + lane;
   }
-  bitonic_sort64(d, c, lane);
+  bitonic_sort64_compact(d, c, lane);
   const bool sentinel = d == __builtin_huge_val();
   if (lane < k) {
     rd[lane] = d;
