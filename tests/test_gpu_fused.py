@@ -80,19 +80,26 @@ def test_fused_f64_tiny_workload_and_determinism():
     assert int(np.argmax(a[2])) == starts[0]
 
 
-@pytest.mark.parametrize("T,L,k", [(300, 3, 6), (2000, 3, 5)])
-def test_fused_constant_series_ties_and_overflow(T, L, k):
-    """Every distance is 0, so every candidate of every tile ties with each
-    row's bound and only the index order decides; the lists are the k
-    smallest indices outside the exclusion zone, as the tie rule requires."""
-    _say(f"[gpu-fused] constant series T={T} L={L} k={k}")
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3", "fp32"])
+@pytest.mark.parametrize("T,L,k", [(300, 3, 6), (2000, 3, 5), (1200, 5, 40)])
+def test_fused_constant_series_ties_and_overflow(T, L, k, prec):
+    """Every distance is 0 (the centred fields vanish), so every candidate of
+    every tile ties with each row's bound and only the index order decides:
+    each recipient's survivors overflow the 64-entry scratch into the sorted
+    register list, and every sort and merge compares equal distances. The
+    lists are the k smallest indices outside the exclusion zone, as the tie
+    rule requires, and the MFMA precisions equal the matrix mode's."""
+    _say(f"[gpu-fused] constant series {prec} T={T} L={L} k={k}")
     Xn = np.full((T, 7), 101300.0, dtype=np.float32)
-    idx, dist, s = _run(Xn, L, k)
+    idx, dist, s = _run(Xn, L, k, prec)
     n = T - L + 1
     for t in range(n):
         want = [j for j in range(n) if abs(j - t) >= L][:k]
         assert idx[t].tolist() == want, t
     assert np.all(dist == 0) and np.all(s == 0)
+    if prec != "fp64":
+        for u, v in zip((idx, dist, s), _run(Xn, L, k, prec, "matrix")):
+            assert np.array_equal(u, v)
 
 
 @pytest.mark.parametrize("shape", ["grid32", "pca13"])
