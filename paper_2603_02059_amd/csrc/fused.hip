@@ -130,7 +130,8 @@ __global__ __launch_bounds__(F64_THREADS) void fused_f64_kernel(
 // time), so that each lane then loads one entry and a ballot filters 64
 // entries against the list's k-th at once -- two memory round trips per
 // batch of slots. A batch with many entries below the k-th is merged into the
-// list by one sort of both, the others by insertion.
+// list by sorts of the list with up to 64 - k of them at a time, the others
+// by insertion.
 constexpr int SEL_WAVES = 4;
 constexpr int SEL_PARK = 1024;
 // a batch with at least this many entries to insert is merged by a sort
@@ -197,9 +198,11 @@ __global__ __launch_bounds__(64 * SEL_WAVES) void select_kernel(
         const bool pass = e < p1 && key_less(d, c, kd, ki);
         const uint64_t m = __ballot(pass);
         const int cnt = __builtin_popcountll(m);
-        if (cnt >= SEL_SORT_MIN && k + cnt <= 64) {
-          // the list (lanes < k) and the passing entries (compacted into
-          // lanes k ..) in one sort; its first k lanes are the new list
+        const int room = 64 - k;  // entries one sort takes beside the list
+        if (cnt >= SEL_SORT_MIN && room >= SEL_SORT_MIN) {
+          // the passing entries, compacted, go in with the list (lanes < k)
+          // up to `room` at a time (lanes k ..), one sort each; its first k
+          // lanes are the new list
           const int pos = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
                                                          __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
           if (pass) {
@@ -207,18 +210,20 @@ __global__ __launch_bounds__(64 * SEL_WAVES) void select_kernel(
             mrg_i[w][pos] = c;
           }
           __builtin_amdgcn_wave_barrier();
-          const int src = lane - k;
-          double md = lane < k ? ed : __builtin_huge_val();
-          int mi = lane < k ? ei : INT_MAX - 64 + lane;
-          if (src >= 0 && src < cnt) {
-            md = mrg_d[w][src];
-            mi = mrg_i[w][src];
+          for (int c0 = 0; c0 < cnt; c0 += room) {
+            const int src = lane - k + c0;
+            double md = lane < k ? ed : __builtin_huge_val();
+            int mi = lane < k ? ei : INT_MAX - 64 + lane;
+            if (lane >= k && src < cnt) {
+              md = mrg_d[w][src];
+              mi = mrg_i[w][src];
+            }
+            bitonic_sort64(md, mi, lane);
+            const bool real = mi < INT_MAX - 64;
+            ed = real ? md : __builtin_huge_val();
+            ei = real ? mi : INT_MAX;
           }
           __builtin_amdgcn_wave_barrier();
-          bitonic_sort64(md, mi, lane);
-          const bool real = mi < INT_MAX - 64;
-          ed = real ? md : __builtin_huge_val();
-          ei = real ? mi : INT_MAX;
         } else if (m) {
           insert_reg(m, d, c, k, ed, ei);
         }
