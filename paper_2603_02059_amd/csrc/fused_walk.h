@@ -90,6 +90,10 @@ __device__ __forceinline__ float prefilter_bound(double bound) {
 // builtins that return the wave's lane mask directly
 constexpr int FCMP_OLE = 5;
 
+// A batch with at least this many candidates below the k-th of a sorted list
+// is merged into it by sorts rather than by one insertion each.
+constexpr int LIST_SORT_MIN = 6;
+
 // Per-wave LDS scratch of a recipient's candidates: up to 64 compacted entries.
 struct EstScratch {
   double* d;  // [64]
@@ -125,7 +129,9 @@ __device__ __forceinline__ void batch_masks(int Q, int q0, int np, int pg, int s
 // the end more than k are sorted (the k smallest kept) and at most k are
 // kept as they are, unsorted. A batch that would take the scratch past 64
 // entries turns it into a sorted list in registers, into which that batch
-// and the later ones are inserted. Returns how many lanes (from 0) hold
+// and the later ones are merged (without a bound, by sorts when many of a
+// batch are below the list's k-th; else one insertion each). Returns how many
+// lanes (from 0) hold
 // entries. The FP64 sums run in increasing m, as the matrix mode's windows
 // start them; for FP32 snapshot distances whose exponents span less than
 // about 29 bits every FP64 sum is exact, so both modes give the same D_L.
@@ -203,7 +209,37 @@ __device__ __forceinline__ int recipient_topk(const float* V, int sp, int sq, in
       const double kd = readlane_d(ed, k - 1);
       const int ki = __builtin_amdgcn_readlane(ei, k - 1);
       const uint64_t m = __ballot(valid && key_less(D, qg, kd, ki));
-      if (m) insert_reg(m, D, qg, k, ed, ei);
+      const int mc = __builtin_popcountll(m);
+      if (!FILTER && mc >= LIST_SORT_MIN && 64 - k >= LIST_SORT_MIN) {
+        // many below the k-th (the first round's unbounded case; the filter
+        // rounds rarely get here and keep their code small): through the
+        // (now free) scratch into sorts of the list with up to 64 - k of them
+        // at a time; each sort's first k lanes are the new list
+        const int pos = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
+        __builtin_amdgcn_wave_barrier();
+        if ((m >> lane) & 1) {
+          sc.d[pos] = D;
+          sc.i[pos] = qg;
+        }
+        __builtin_amdgcn_wave_barrier();
+        for (int c0 = 0; c0 < mc; c0 += 64 - k) {
+          const int src = lane - k + c0;
+          double md = lane < k ? ed : __builtin_huge_val();
+          int mi = lane < k ? ei : INT_MAX - 64 + lane;
+          if (lane >= k && src < mc) {
+            md = sc.d[src];
+            mi = sc.i[src];
+          }
+          bitonic_sort64(md, mi, lane);
+          const bool real = mi < INT_MAX - 64;
+          ed = real ? md : __builtin_huge_val();
+          ei = real ? mi : INT_MAX;
+        }
+        __builtin_amdgcn_wave_barrier();
+      } else if (m) {
+        insert_reg(m, D, qg, k, ed, ei);
+      }
     }
   }
   if (listed) return __builtin_popcountll(__ballot(lane < k && ei != INT_MAX));
