@@ -96,16 +96,52 @@ def gram_flops(T: int, D: int, prec: str) -> float:
     return passes * 2.0 * D * T * (T + 1) / 2.0
 
 
-def band_tiles(T: int, L_min: int, L_max: int, rb: int) -> int:
-    """256 x 256 Gram tiles of all band passes: pass t0 contracts its
-    ceil(rows / 256) block-rows I against the block-columns J >= t0 // 256 + I
-    (the tiles that hold entries above the diagonal)."""
-    n, nb, tiles = T - L_min + 1, -(-T // 256), 0
-    for t0 in range(0, n, rb):
-        srows = min(min(rb, n - t0) + L_max - 1, T - t0)
-        nbi, nbc = -(-srows // 256), nb - t0 // 256
-        tiles += nbi * nbc - nbi * (nbi - 1) // 2
-    return tiles
+def _pass_tiles(T: int, L_max: int, t0: int, nt: int) -> int:
+    """Tiles of a band pass of nt trajectories from t0: its ceil(rows / 256)
+    block-rows I against the block-columns J >= t0 // 256 + I (the tiles that
+    hold entries above the diagonal)."""
+    srows = min(nt + L_max - 1, T - t0)
+    nbi, nbc = -(-srows // 256), -(-T // 256) - t0 // 256
+    return nbi * nbc - nbi * (nbi - 1) // 2
+
+
+def band_passes(T: int, L_min: int, L_max: int, rb: int, Dpad: int) -> list:
+    """The band passes' (t0, rows), as the plan places them: starts on
+    multiples of 8, at most rb rows each, minimising the passes' rounds of 256
+    tiles plus 1 + 8192 / Dpad rounds per pass (same rule, same order of
+    evaluation as the library's planner)."""
+    n = T - L_min + 1
+    lam = 1.0 + 8192.0 / Dpad
+    npos = (n + 7) // 8
+    state = lambda t: npos if t >= n else t // 8
+    cost, nxt = [0.0] * (npos + 1), [n] * (npos + 1)
+    for i in range(npos - 1, -1, -1):
+        t0, left = 8 * i, n - 8 * i
+        best, bt1, nbi = None, n, 1
+        while True:
+            nt, last = (nbi * 256 - (L_max - 1)) // 8 * 8, False
+            if nt >= rb:
+                nt, last = rb, True
+            if nt >= left:
+                nt, last = left, True
+            if nt > 0:
+                c = -(-_pass_tiles(T, L_max, t0, nt) // 256) + lam + cost[state(t0 + nt)]
+                if best is None or c < best:
+                    best, bt1 = c, t0 + nt
+            if last:
+                break
+            nbi += 1
+        cost[i], nxt[i] = best, bt1
+    out, t = [], 0
+    while t < n:
+        out.append((t, nxt[state(t)] - t))
+        t = nxt[state(t)]
+    return out
+
+
+def band_tiles(T: int, L_min: int, L_max: int, rb: int, Dpad: int) -> int:
+    """256 x 256 Gram tiles of all band passes."""
+    return sum(_pass_tiles(T, L_max, t0, nt) for t0, nt in band_passes(T, L_min, L_max, rb, Dpad))
 
 
 def window_bytes(T: int, L: int, rows: int = 8) -> dict:
@@ -531,13 +567,18 @@ def main():
         r = time_path(tk, torch, X, w, "bf16x3", args.compare_steps, args.warmup,
                       row_batch=args.band_rows)
         rb = args.band_rows
-        flops = 3 * 2.0 * w.D * 256 * 256 * band_tiles(w.T, w.L, w.L, rb)
-        band = {"row_batch": rb, "ms_per_step": r["ms_per_step"],
+        Dpad = -(-w.D // 32) * 32  # the BF16x3 Gram's contraction depth
+        passes = band_passes(w.T, w.L, w.L, rb, Dpad)
+        ntiles = band_tiles(w.T, w.L, w.L, rb, Dpad)
+        flops = 3 * 2.0 * Dpad * 256 * 256 * ntiles
+        band = {"row_batch": rb, "passes": len(passes),
+                "gram_rounds": sum(-(-_pass_tiles(w.T, w.L, t0, nt) // 256) for t0, nt in passes),
+                "ms_per_step": r["ms_per_step"],
                 "pairs_per_s": pairs / (r["ms_per_step"] * 1e-3),
                 "passes_ms": r["stage_ms"]["gram"],
                 "mfma_work_vs_algorithmic": flops / gram_flops(w.T, w.D, "bf16x3"),
                 "gram_tiles_vs_whole_matrix":
-                    band_tiles(w.T, w.L, w.L, rb) / (-(-w.T // 256) * (-(-w.T // 256) + 1) / 2),
+                    ntiles / (-(-w.T // 256) * (-(-w.T // 256) + 1) / 2),
                 "workspace_GiB": r["ws_bytes"] / 2 ** 30,
                 "whole_matrix_workspace_GiB": results.get("bf16x3", r)["ws_bytes"] / 2 ** 30}
         if "bf16x3" in results:

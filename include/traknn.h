@@ -130,8 +130,10 @@ extern "C" {
  *               contracted. > 0, a multiple of 8: band mode (row-batched
  *               streaming, for T whose matrix does not fit; the paper names
  *               out-of-core computation as future work, Sec. 7). Pass p owns
- *               the trajectories t0 .. t0 + row_batch - 1 and computes the
- *               rows t0 .. t0 + row_batch + L_max - 2 of the matrix against
+ *               the trajectories t0 .. t1 - 1, at most row_batch of them (the
+ *               plan places the pass starts on multiples of 8 so that the
+ *               passes' partly idle last rounds of tiles cost least), and
+ *               computes the rows t0 .. t1 + L_max - 2 of the matrix against
  *               the columns from t0 on, only the 256 x 256 tiles holding
  *               entries above the diagonal, stored as rows and transposed.
  *               Its rows' later candidates come from the rows, and every

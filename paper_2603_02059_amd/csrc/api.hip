@@ -150,6 +150,53 @@ void plan_fused(traknn_plan_s* p) {
   }
 }
 
+// Band passes: the starts t0 of passes of at most rb rows, on multiples of 8
+// (the chunk-norm loads' alignment). Each pass's Gram launch ends with a
+// partly idle round of 256 tiles, so the starts minimise, by dynamic
+// programming from the last row back, the passes' rounds plus lambda rounds
+// per pass: a pass's own windows and merge cost about the same at any D,
+// while a round of tiles grows with D, so lambda = 1 + 8192 / Dpad. A pass of
+// nt rows from t0 covers nbi = ceil((nt + L_max - 1) / 256) block-rows against
+// the block-columns from t0 / 256 on; for each nbi only the longest such pass
+// is tried.
+void plan_band_passes(traknn_plan_s* p) {
+  const int64_t T = p->T, np0 = p->np0, rb = p->rb;
+  const int64_t Lm1 = p->cfg.L_max - 1;
+  auto rounds = [&](int64_t t0, int64_t nt) {
+    const int64_t srows = nt + Lm1 < T - t0 ? nt + Lm1 : T - t0;
+    const int64_t nbi = (srows + GRAM_TILE - 1) / GRAM_TILE;
+    const int64_t nbc = p->nb - t0 / GRAM_TILE;
+    return (double)((nbi * nbc - nbi * (nbi - 1) / 2 + 255) / 256);
+  };
+  const double lambda = 1.0 + 8192.0 / (double)p->Dpad;
+  const int64_t npos = (np0 + 7) / 8;  // state i < npos: a pass starts at 8 i; npos: the end
+  auto state = [&](int64_t t) { return t >= np0 ? npos : t / 8; };
+  std::vector<double> cost(npos + 1, 0.0);
+  std::vector<int64_t> next(npos + 1, np0);
+  for (int64_t i = npos - 1; i >= 0; --i) {
+    const int64_t t0 = 8 * i, left = np0 - t0;
+    double best = 0.0;
+    int64_t bt1 = np0;
+    bool any = false;
+    for (int64_t nbi = 1;; ++nbi) {
+      int64_t nt = (nbi * GRAM_TILE - Lm1) / 8 * 8;
+      bool last = false;
+      if (nt >= rb) nt = rb, last = true;
+      if (nt >= left) nt = left, last = true;
+      if (nt > 0) {
+        const int64_t t1 = t0 + nt;
+        const double c = rounds(t0, nt) + lambda + cost[state(t1)];
+        if (!any || c < best) best = c, bt1 = t1, any = true;
+      }
+      if (last) break;
+    }
+    cost[i] = best;
+    next[i] = bt1;
+  }
+  p->band_t0.clear();
+  for (int64_t t = 0; t < np0; t = next[state(t)]) p->band_t0.push_back(t);
+}
+
 void plan_layout(traknn_plan_s* p) {
   Layout& L = p->lay;
   size_t o = 0;
@@ -324,9 +371,11 @@ int enqueue_knn(traknn_plan_s* plan, const float* X, int64_t ldx, void* workspac
     double* cpart_d = at<double>(workspace, L.cpart_d);
     int32_t* cpart_i = at<int32_t>(workspace, L.cpart_i);
     const int64_t T = plan->T, np0 = plan->np0;
-    for (int64_t t0 = 0; t0 < np0; t0 += plan->rb) {
-      const int64_t nt = plan->rb < np0 - t0 ? plan->rb : np0 - t0;
-      const int64_t t1 = t0 + nt;
+    const size_t npass = plan->band_t0.size();
+    for (size_t pi = 0; pi < npass; ++pi) {
+      const int64_t t0 = plan->band_t0[pi];
+      const int64_t t1 = pi + 1 < npass ? plan->band_t0[pi + 1] : np0;
+      const int64_t nt = t1 - t0;
       const int64_t srows = nt + c.L_max - 1 < T - t0 ? nt + c.L_max - 1 : T - t0;
       const int nbi = (int)((srows + GRAM_TILE - 1) / GRAM_TILE);
       const int J0 = (int)(t0 / GRAM_TILE);
@@ -485,6 +534,14 @@ int traknn_plan(const traknn_config* cfg, traknn_plan_t* out,
   } else if (!plan_window(p)) {
     delete p;
     return TRAKNN_ERR_UNSUPPORTED;
+  }
+  if (p->rb) {
+    try {
+      plan_band_passes(p);
+    } catch (...) {  // no exception crosses the C ABI
+      delete p;
+      return TRAKNN_ERR_INVALID_ARG;
+    }
   }
   plan_layout(p);
   *out = p;

@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <vector>
 
 #include "traknn.h"
 
@@ -107,7 +108,8 @@ struct traknn_plan_s {
   int NL;            // L_max - L_min + 1
   int nb;            // ceil(T / GRAM_TILE) block-columns
   int64_t ntiles;    // nb (nb + 1) / 2 upper-triangular tile pairs
-  int64_t rb;        // band mode: trajectory rows per pass (0: whole matrix)
+  int64_t rb;        // band mode: at most this many trajectory rows per pass (0: whole matrix)
+  std::vector<int64_t> band_t0;  // band mode: the passes' first trajectory rows
   int64_t band_rows; // band mode: rows of S held, rb + L_max - 1 (at most T)
   int64_t ldST;      // band mode: row stride of the transposed band, floats
   int tchunks;       // partial column-sum blocks of the sampled rows

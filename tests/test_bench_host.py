@@ -37,23 +37,33 @@ def test_window_bytes():
     assert wb["design_bytes"] == 4.0 * 100 * 100 * 12 / 8
 
 
+@pytest.mark.parametrize("Dpad", [8192, 32])
 @pytest.mark.parametrize("T,L,rb", [(700, 4, 248), (700, 4, 8), (520, 16, 504), (1000, 2, 512),
                                     (27394, 5, 4088)])
-def test_band_tiles(T, L, rb):
+def test_band_tiles(T, L, rb, Dpad):
+    # the planned passes: contiguous, starting on multiples of 8, at most rb
+    # rows each, covering the n trajectories
+    n, nb = T - L + 1, -(-T // 256)
+    passes = bench.band_passes(T, L, L, rb, Dpad)
+    assert passes[0][0] == 0 and sum(nt for _, nt in passes) == n
+    for (t0, nt), (t1, _) in zip(passes, passes[1:] + [(n, 0)]):
+        assert t0 % 8 == 0 and 0 < nt <= rb and t0 + nt == t1
     # brute force: pass t0 holds rows t0 .. t0 + srows - 1 in 256-row block-rows
     # aligned to t0 and 256-column blocks aligned to 0; it contracts the tiles
     # with an entry above the diagonal, and together the passes hold every
     # entry (r, c), c > r, that a trajectory window reads
-    n, nb = T - L + 1, -(-T // 256)
-    tiles, covered = 0, np.zeros(T, bool)
-    for t0 in range(0, n, rb):
-        srows = min(min(rb, n - t0) + L - 1, T - t0)
+    tiles, rounds, covered = 0, 0, np.zeros(T, bool)
+    for t0, nt in passes:
+        srows = min(nt + L - 1, T - t0)
         nbi = -(-srows // 256)
+        ptiles = 0
         for I in range(nbi):
             r_lo = t0 + 256 * I
             for J in range(nb):
                 if 256 * J + 255 > r_lo:  # some column above the tile's first row
-                    tiles += 1
+                    ptiles += 1
+        tiles += ptiles
+        rounds += -(-ptiles // 256)
         if T <= 1000:
             r = np.arange(t0, t0 + srows)[:, None]
             c = np.arange(T)[None, :]
@@ -62,8 +72,16 @@ def test_band_tiles(T, L, rb):
             # contracted tile
             assert np.all((J >= t0 // 256 + I) | (c <= r))
             covered[t0:t0 + srows] = True
-    assert bench.band_tiles(T, L, L, rb) == tiles
+    assert bench.band_tiles(T, L, L, rb, Dpad) == tiles
     assert T > 1000 or covered.all()
+    # the plan costs no more than passes of exactly rb rows (rounds of 256
+    # tiles plus 1 + 8192 / Dpad rounds per pass), which it also considers
+    lam = 1.0 + 8192.0 / Dpad
+    fixed = [(t0, min(rb, n - t0)) for t0 in range(0, n, rb)]
+    fixed_cost = sum(-(-bench._pass_tiles(T, L, t0, nt) // 256) + lam for t0, nt in fixed)
+    assert rounds + lam * len(passes) <= fixed_cost + 1e-9
+    if (T, L, rb, Dpad) == (27394, 5, 4088, 8192):
+        assert (len(passes), rounds) == (7, 26)  # fixed passes: 7 and 28
 
 
 @pytest.mark.parametrize("T,D,L,k,prec,rb", [
