@@ -108,8 +108,9 @@ def _pass_tiles(T: int, L_max: int, t0: int, nt: int) -> int:
 def band_passes(T: int, L_min: int, L_max: int, rb: int, Dpad: int) -> list:
     """The band passes' (t0, rows), as the plan places them: starts on
     multiples of 8, at most rb rows each, minimising the passes' rounds of 256
-    tiles plus 1 + 8192 / Dpad rounds per pass (same rule, same order of
-    evaluation as the library's planner)."""
+    tiles plus 1 + 8192 / Dpad rounds per pass, trying for each start the
+    longest pass of each of the 16 largest block-row counts (same rule, same
+    order of evaluation as the library's planner)."""
     n = T - L_min + 1
     lam = 1.0 + 8192.0 / Dpad
     npos = (n + 7) // 8
@@ -117,7 +118,8 @@ def band_passes(T: int, L_min: int, L_max: int, rb: int, Dpad: int) -> list:
     cost, nxt = [0.0] * (npos + 1), [n] * (npos + 1)
     for i in range(npos - 1, -1, -1):
         t0, left = 8 * i, n - 8 * i
-        best, bt1, nbi = None, n, 1
+        nbi_max = -(-(min(rb, left) + L_max - 1) // 256)
+        best, bt1, nbi = None, n, max(1, nbi_max - 15)
         while True:
             nt, last = (nbi * 256 - (L_max - 1)) // 8 * 8, False
             if nt >= rb:

@@ -158,7 +158,8 @@ void plan_fused(traknn_plan_s* p) {
 // while a round of tiles grows with D, so lambda = 1 + 8192 / Dpad. A pass of
 // nt rows from t0 covers nbi = ceil((nt + L_max - 1) / 256) block-rows against
 // the block-columns from t0 / 256 on; for each nbi only the longest such pass
-// is tried.
+// is tried, and only the 16 largest nbi (all of them up to passes of 4096
+// rows), so that planning stays linear in T.
 void plan_band_passes(traknn_plan_s* p) {
   const int64_t T = p->T, np0 = p->np0, rb = p->rb;
   const int64_t Lm1 = p->cfg.L_max - 1;
@@ -178,7 +179,9 @@ void plan_band_passes(traknn_plan_s* p) {
     double best = 0.0;
     int64_t bt1 = np0;
     bool any = false;
-    for (int64_t nbi = 1;; ++nbi) {
+    const int64_t span = rb < left ? rb : left;
+    const int64_t nbi_max = (span + Lm1 + GRAM_TILE - 1) / GRAM_TILE;
+    for (int64_t nbi = nbi_max > 16 ? nbi_max - 15 : 1;; ++nbi) {
       int64_t nt = (nbi * GRAM_TILE - Lm1) / 8 * 8;
       bool last = false;
       if (nt >= rb) nt = rb, last = true;
