@@ -293,6 +293,17 @@ int traknn_score_backward(traknn_plan_t plan, const float* X, int64_t ldx,
  * Errors: INVALID_ARG for NULL. */
 int traknn_backward_workspace(traknn_plan_t plan, size_t* bytes);
 
+/* Band mode's passes, as the plan placed them (row_batch above): the first
+ * trajectory row of each pass, in increasing order, each pass at most
+ * row_batch rows and the last ending at T - L_min + 1. Pure host call.
+ *   starts [out] host array; the first min(*count, cap) starts are written
+ *                (may be NULL when cap is 0).
+ *   cap    [in]  entries starts can hold.
+ *   count  [out] number of passes (0 in the whole-matrix and fused modes).
+ * Errors: INVALID_ARG for a NULL plan or count, a negative cap, or NULL
+ * starts with cap > 0. */
+int traknn_band_passes(traknn_plan_t plan, int64_t* starts, int64_t cap, int64_t* count);
+
 /* Static description of a status code; never NULL. */
 const char* traknn_status_string(int status);
 

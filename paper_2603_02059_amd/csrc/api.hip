@@ -662,4 +662,12 @@ int traknn_backward_workspace(traknn_plan_t plan, size_t* bytes) {
   return TRAKNN_OK;
 }
 
+int traknn_band_passes(traknn_plan_t plan, int64_t* starts, int64_t cap, int64_t* count) {
+  if (!plan || !count || cap < 0 || (cap > 0 && !starts)) return TRAKNN_ERR_INVALID_ARG;
+  const int64_t n = (int64_t)plan->band_t0.size();
+  for (int64_t i = 0; i < n && i < cap; ++i) starts[i] = plan->band_t0[i];
+  *count = n;
+  return TRAKNN_OK;
+}
+
 }  // extern "C"

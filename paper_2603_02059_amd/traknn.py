@@ -45,7 +45,7 @@ EXPORTS = ("traknn_plan", "traknn_plan_destroy", "traknn_knn", "traknn_knn_noall
            "traknn_score",
            "traknn_score_prefix", "traknn_local_dim", "traknn_score_backward",
            "traknn_backward_workspace", "traknn_status_string", "traknn_set_timing",
-           "traknn_stage_times")
+           "traknn_stage_times", "traknn_band_passes")
 
 
 class TraknnError(RuntimeError):
@@ -80,6 +80,7 @@ def _load() -> ctypes.CDLL:
     lib.traknn_local_dim.argtypes = [vp, vp, vp, vp]
     lib.traknn_score_backward.argtypes = [vp, vp, i64, vp, vp, vp, i64, vp, sz, vp]
     lib.traknn_backward_workspace.argtypes = [vp, ctypes.POINTER(sz)]
+    lib.traknn_band_passes.argtypes = [vp, ctypes.POINTER(i64), i64, ctypes.POINTER(i64)]
     lib.traknn_status_string.argtypes = [i32]
     lib.traknn_status_string.restype = ctypes.c_char_p
     lib.traknn_set_timing.argtypes = [vp, i32]
@@ -208,6 +209,15 @@ def traknn_backward_workspace(plan) -> int:
     return b.value
 
 
+def traknn_band_passes(plan) -> list:
+    """Band mode's pass starts as the plan placed them ([] outside band mode)."""
+    n = ctypes.c_int64()
+    _ck(_lib.traknn_band_passes(plan, None, 0, ctypes.byref(n)), "traknn_band_passes")
+    buf = (ctypes.c_int64 * max(n.value, 1))()
+    _ck(_lib.traknn_band_passes(plan, buf, n.value, ctypes.byref(n)), "traknn_band_passes")
+    return list(buf[:n.value])
+
+
 def traknn_status_string(code: int) -> str:
     return status_string(code)
 
@@ -312,6 +322,10 @@ class Plan:
                               device=self.device)
         traknn_local_dim(self.handle, dist, out, stream)
         return out
+
+    def band_passes(self):
+        """Band mode's pass starts as the plan placed them ([] outside band mode)."""
+        return traknn_band_passes(self.handle)
 
     def release_workspace(self):
         """Free the forward workspace; backward then allocates only the small

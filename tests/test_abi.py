@@ -267,3 +267,43 @@ def test_backward_workspace_is_a_small_prefix():
         n = T - L + 1
         assert 4 * (3 * n + k * n) <= bw <= ws
         assert bw < ws / 20
+
+
+@pytest.mark.parametrize("T,D,L,rb", [(27394, 8192, 5, 4088), (27394, 32, 5, 4088), (700, 1024, 4, 248),
+                                      (700, 1024, 4, 8), (520, 1024, 16, 504), (1000, 1024, 2, 512),
+                                      (300000, 1024, 5, 16376)])
+def test_band_passes_query(T, D, L, rb):
+    """The plan's band passes, read through the C ABI, are the ones bench.py's
+    mirror of the planner computes (the tile counts it reports rely on it),
+    and they cover the trajectories in passes of at most row_batch rows."""
+    import bench
+    h, _ = tk.traknn_plan(T, D, L, L, 10, "bf16x3", rb)
+    try:
+        starts = tk.traknn_band_passes(h)
+    finally:
+        tk.traknn_plan_destroy(h)
+    want = [t0 for t0, _ in bench.band_passes(T, L, L, rb, -(-D // 32) * 32)]
+    assert starts == want
+    ends = starts[1:] + [T - L + 1]
+    assert starts[0] == 0 and all(s % 8 == 0 and 0 < e - s <= rb for s, e in zip(starts, ends))
+
+
+def test_band_passes_query_arguments():
+    h, _ = tk.traknn_plan(2000, 64, 3, 3, 7, "bf16x3", 0)
+    n = ctypes.c_int64(-1)
+    try:
+        lib = tk._lib
+        assert lib.traknn_band_passes(h, None, 0, ctypes.byref(n)) == 0 and n.value == 0
+        assert lib.traknn_band_passes(h, None, 0, None) == -1
+        assert lib.traknn_band_passes(h, None, 1, ctypes.byref(n)) == -1
+        assert lib.traknn_band_passes(h, None, -1, ctypes.byref(n)) == -1
+        assert lib.traknn_band_passes(None, None, 0, ctypes.byref(n)) == -1
+    finally:
+        tk.traknn_plan_destroy(h)
+    h, _ = tk.traknn_plan(2000, 64, 3, 3, 7, "bf16x3", 512)
+    try:
+        buf = (ctypes.c_int64 * 1)()
+        assert tk._lib.traknn_band_passes(h, buf, 1, ctypes.byref(n)) == 0
+        assert n.value > 1 and buf[0] == 0  # the count is the full one, the copy capped
+    finally:
+        tk.traknn_plan_destroy(h)
