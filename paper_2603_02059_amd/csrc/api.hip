@@ -114,7 +114,9 @@ void plan_fused(traknn_plan_s* p) {
   g.blo = g.bhi = 0;
   // Round ends: each launch's last wave of tiles is partly idle, so the
   // second and third rounds end where the four launches need the fewest
-  // waves of resident tiles, ties kept nearest the default ends.
+  // waves of resident tiles, ties kept nearest the default ends. The FP64
+  // tiles are half as wide, so their offsets (ranges and defaults) double to
+  // reach as far in trajectories.
   const int64_t conc = (int64_t)NUM_CU * (f64 ? FUSED_F64_PER_CU : 1);
   auto tiles = [&](int lo, int hi) {
     hi = hi < g.nbt ? hi : g.nbt;
@@ -127,15 +129,16 @@ void plan_fused(traknn_plan_s* p) {
     return waves(0, FUSED_FIRST_END) + waves(FUSED_FIRST_END, e2) + waves(e2, e3) +
            waves(e3, g.nbt);
   };
+  const int sc = f64 ? 2 : 1;
   auto dist = [&](int e2, int e3) {
-    const int a = e2 - FUSED_END_DEFAULT[0], b = e3 - FUSED_END_DEFAULT[1];
+    const int a = e2 - sc * FUSED_END_DEFAULT[0], b = e3 - sc * FUSED_END_DEFAULT[1];
     return 4 * (a < 0 ? -a : a) + (b < 0 ? -b : b);
   };
-  g.rend[0] = FUSED_END_DEFAULT[0];
-  g.rend[1] = FUSED_END_DEFAULT[1];
+  g.rend[0] = sc * FUSED_END_DEFAULT[0];
+  g.rend[1] = sc * FUSED_END_DEFAULT[1];
   int64_t best = cost(g.rend[0], g.rend[1]);
-  for (int e2 = 6; e2 <= 12; ++e2)
-    for (int e3 = e2 + 4 > 24 ? e2 + 4 : 24; e3 <= 48; ++e3) {
+  for (int e2 = 6 * sc; e2 <= 12 * sc; ++e2)
+    for (int e3 = e2 + 4 > 24 * sc ? e2 + 4 : 24 * sc; e3 <= 48 * sc; ++e3) {
       const int64_t cst = cost(e2, e3);
       if (cst < best || (cst == best && dist(e2, e3) < dist(g.rend[0], g.rend[1]))) {
         best = cst;

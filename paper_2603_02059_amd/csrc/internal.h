@@ -66,7 +66,7 @@ constexpr int FUSED_FIRST_END = 2;
 static_assert(FUSED_FIRST_END >= 2, "the first round covers tile offsets 0 and 1");
 // Ends of the second and third rounds: by default 8 and 32; the planner moves
 // them within [6, 12] and [24, 48] to fill the launches' last waves of tiles.
-constexpr int FUSED_END_DEFAULT[2] = {8, 32};
+constexpr int FUSED_END_DEFAULT[2] = {12, 48};
 // Compute units of an MI355X: the tiles resident at once are this many times
 // the workgroups of a fused tile kernel per CU (1 MFMA, 2 FP64).
 constexpr int NUM_CU = 256;
